@@ -1,0 +1,288 @@
+"""Benchmark of the F-COO hot path on one MI355X.
+
+Workload (one "step"): the 3-order Zipf(1.1) tensor 100,000 x 80,000 x 60,000
+with 20M unique nonzeros (values U(0,1), float32), SpMTTKRP and SpTTM in
+every mode at R = 16 and R = 32, float32 factors N(0,1) -- 12 operations.
+Inputs and F-COO arrays are resident in HBM before the timed region.
+
+value = algorithmic bytes of the 12 operations / step time (GB/s): per
+nonzero the index and value streams, the bf / sf flags, one factor row per
+product mode gathered, plus the output rows written (the dense unfolding and
+Khatri-Rao product that the method avoids are not counted).
+
+Prints one JSON line.  The roofline object describes the dominant kernel (the
+SpMTTKRP or SpTTM tile kernel with the largest total time), timed alone with
+HIP events that the library records around each tile-kernel launch.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "SpMTTKRP GB/s & GFLOP/s (%HBM peak), CP-ALS s/iter, BF16 vs FP32 at stated fit"
+WORKLOAD_CFG = 1
+KERNEL_SOURCES = ["fcoo_segscan.h", "fcoo_device.h", "fcoo_seg_dispatch.h", "fcoo_ops.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1705_09905_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def op_bytes(op, Z, N, R, nseg, In, P, sf=4):
+    """Algorithmic bytes of one SpMTTKRP / SpTTM on one mode."""
+    flags = (Z + 7) // 8 + 4 * ((P + 31) // 32)
+    if op == "mttkrp":
+        return 4 * Z * (N - 1) + 4 * Z + flags + 4 * nseg + Z * (N - 1) * R * sf + 4 * In * R
+    return 4 * Z + 4 * Z + flags + Z * R * sf + 4 * nseg * R
+
+
+def op_flops(op, Z, N, R):
+    return Z * R * N if op == "mttkrp" else 2 * Z * R
+
+
+class HipEvents:
+    """hipEvent_t pool through the HIP runtime already loaded by torch."""
+
+    def __init__(self):
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.events = []
+
+    def new(self):
+        e = C.c_void_p()
+        rc = self.hip.hipEventCreate(C.byref(e))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed: {rc}")
+        self.events.append(e)
+        return e
+
+    def ms(self, a, b):
+        out = C.c_float()
+        rc = self.hip.hipEventElapsedTime(C.byref(out), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(out.value)
+
+    def close(self):
+        for e in self.events:
+            self.hip.hipEventDestroy(e)
+        self.events = []
+
+
+def cpu_baseline(t, Rs, sample_nnz, threads):
+    """The float64 C oracle (plain COO loops, OpenMP) on a bounded sample of
+    the same workload: the first `sample_nnz` nonzeros of the shuffled list."""
+    from oracle import cpu
+    import synth
+    Zs = min(sample_nnz, t.nnz)
+    idx = [np.ascontiguousarray(i[:Zs]) for i in t.idx]
+    vals = t.vals[:Zs].astype(np.float32).astype(np.float64)
+    N = t.order
+    total_bytes, total_s, used = 0, 0.0, 1
+    groups = [cpu.ttm_group(t.dims, idx, m) for m in range(N)]
+    for R in Rs:
+        F = [f.astype(np.float32).astype(np.float64) for f in synth.factors(t.dims, R, WORKLOAD_CFG)]
+        for m in range(N):
+            cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads)   # warm-up
+            t0 = time.perf_counter()
+            _, used = cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads, return_threads=True)
+            total_s += time.perf_counter() - t0
+            nseg = len(np.unique(idx[m]))
+            total_bytes += op_bytes("mttkrp", Zs, N, R, nseg, t.dims[m], -(-Zs // 16))
+            t0 = time.perf_counter()
+            fib, _, used2 = cpu.ttm(t.dims, idx, vals, F[m], m, group=groups[m], nthreads=threads,
+                                    return_threads=True)
+            total_s += time.perf_counter() - t0
+            total_bytes += op_bytes("ttm", Zs, N, R, fib.shape[0], t.dims[m], -(-Zs // 16))
+    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
+                      f"every mode, R in {list(Rs)}, float64, {total_s:.2f} s timed "
+                      f"(fibre grouping excluded)"}
+
+
+def load_traffic(khash):
+    p = os.path.join(ROOT, "profiles", "traffic_spmttkrp_zipf20M_r32.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != khash:
+        return None
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ranks", default="16,32")
+    ap.add_argument("--nnz", type=int, default=0, help="override the nonzero count (quick runs)")
+    ap.add_argument("--threadlen", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1705_09905_amd import Tensor, _lib
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    Rs = [int(r) for r in args.ranks.split(",")]
+    t0 = time.time()
+    t = synth.config_tensor(WORKLOAD_CFG, nnz=args.nnz or None)
+    log(f"generated {t.name} Z={t.nnz} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    h = Tensor(t.idx, t.vals, t.dims)
+    t0 = time.time()
+    for m in range(t.order):
+        for op in ("mttkrp", "ttm"):
+            h.build(m, op, threadlen=args.threadlen, tile_nnz=args.tile)
+    build_s = time.time() - t0
+    log(f"F-COO built and uploaded (6 builds) in {build_s:.1f}s")
+    infos = {(op, m): h.info(m, op) for m in range(t.order) for op in ("mttkrp", "ttm")}
+
+    facs = {R: [torch.tensor(f.astype(np.float32), device=dev)
+                for f in synth.factors(t.dims, R, WORKLOAD_CFG)] for R in Rs}
+    outs = {}
+    for R in Rs:
+        for m in range(t.order):
+            outs[("mttkrp", m, R)] = torch.empty((t.dims[m], R), dtype=torch.float32, device=dev)
+            outs[("ttm", m, R)] = torch.empty((infos[("ttm", m)]["nseg"], R), dtype=torch.float32,
+                                              device=dev)
+    launches = [(op, m, R) for R in Rs for m in range(t.order) for op in ("mttkrp", "ttm")]
+
+    def run(op, m, R):
+        if op == "mttkrp":
+            h.spmttkrp(m, facs[R], out=outs[(op, m, R)])
+        else:
+            h.spttm(m, facs[R][m], out=outs[(op, m, R)])
+
+    ev = HipEvents()
+    for _ in range(args.warmup):
+        for L in launches:
+            run(*L)
+    torch.cuda.synchronize()
+
+    pairs = []
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        for L in launches:
+            a, b = ev.new(), ev.new()
+            _lib.check(_lib.fcoo_set_tile_events(h.handle, a, b))
+            run(*L)
+            pairs.append((L, a, b))
+    end.record()
+    torch.cuda.synchronize()
+    _lib.check(_lib.fcoo_set_tile_events(h.handle, None, None))
+    total_ms = start.elapsed_time(end)
+    ms_per_step = total_ms / args.steps
+
+    N = t.order
+    per = {}
+    for L, a, b in pairs:
+        per.setdefault(L, []).append(ev.ms(a, b))
+    ev.close()
+    step_bytes, step_flops = 0, 0
+    classes = {}
+    detail = []
+    for (op, m, R) in launches:
+        inf = infos[(op, m)]
+        B = op_bytes(op, t.nnz, N, R, inf["nseg"], t.dims[m], inf["npart"])
+        F = op_flops(op, t.nnz, N, R)
+        step_bytes += B
+        step_flops += F
+        d = float(np.mean(per[(op, m, R)]))
+        c = classes.setdefault((op, R), {"bytes": 0, "ms": 0.0, "n": 0})
+        c["bytes"] += B
+        c["ms"] += d
+        c["n"] += 1
+        detail.append({"op": op, "mode": m, "R": R, "tile_ms": round(d, 4),
+                       "GBps": round(B / d / 1e6, 1), "nseg": inf["nseg"], "nfix": inf["nfix"]})
+    if args.detail:
+        for d in detail:
+            log(json.dumps(d))
+    dom = max(classes, key=lambda k: classes[k]["ms"])
+    dc = classes[dom]
+    achieved = dc["bytes"] / dc["n"] / (dc["ms"] / dc["n"]) / 1e6     # GB/s per launch
+    khash = kernel_hash()
+    tr = load_traffic(khash)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": (tr["bytes_per_launch"] if tr else None),
+                "kernel": f"seg_tile_kernel ({'SpMTTKRP' if dom[0] == 'mttkrp' else 'SpTTM'}, R={dom[1]}, "
+                          f"float32, per-mode launch)",
+                "bytes_per_launch": int(dc["bytes"] / dc["n"]),
+                "avg_launch_ms": round(dc["ms"] / dc["n"], 4)}
+    value = step_bytes / (ms_per_step / 1e3) / 1e9
+    mt = {R: classes[("mttkrp", R)] for R in Rs}
+    tt = {R: classes[("ttm", R)] for R in Rs}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{t.name}: SpMTTKRP + SpTTM, every mode, R in {Rs}",
+                   "dims": t.dims, "nnz": t.nnz, "ranks": Rs, "threadlen": args.threadlen,
+                   "tile_nnz": args.tile},
+        "gflops": round(step_flops / (ms_per_step / 1e3) / 1e9, 1),
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
+        "spmttkrp_GBps": {str(R): round(mt[R]["bytes"] / mt[R]["ms"] / 1e6, 1) for R in Rs},
+        "spttm_GBps": {str(R): round(tt[R]["bytes"] / tt[R]["ms"] / 1e6, 1) for R in Rs},
+        "spmttkrp_ms_per_mode": {str(R): round(mt[R]["ms"] / mt[R]["n"], 4) for R in Rs},
+        "roofline": roofline,
+        "build_s": round(build_s, 2),
+        "kernel_hash": khash,
+    }
+    if not args.no_cpu:
+        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        os.environ.setdefault("OMP_PROC_BIND", "close")
+        t0 = time.time()
+        out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads)
+        log(f"cpu baseline in {time.time() - t0:.1f}s")
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

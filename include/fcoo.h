@@ -1,0 +1,255 @@
+/*
+ * fcoo.h -- C ABI of the F-COO sparse tensor library for AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The library implements the unified sparse tensor method of "A Unified
+ * Optimization Approach for Sparse Tensor Operations on GPUs" (Liu, Wen,
+ * Sarwate, Mehri Dehnavi): the flagged-coordinate (F-COO) storage format
+ * (Sec. IV-B), and one-shot SpMTTKRP / SpTTM kernels that reduce with a
+ * segmented scan instead of atomics (Sec. IV-C, IV-D), driving CP-ALS
+ * (Algorithm 1).  It adds gradient-based sparse CP (model at the nonzeros,
+ * residual SpMTTKRP) and a BF16 factor-storage form.
+ *
+ * Conventions for every entry point:
+ *   - Modes are 0-based: the paper's "mode-1" is mode 0.
+ *   - Dense matrices (factors, M, Y, U) are row-major with leading dimension
+ *     R: element (i, r) is at offset i * R + r.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it and the call returns without waiting,
+ *     except where stated (fcoo_build waits for its upload; fcoo_cp_als_iter
+ *     waits for the 8-byte fit).
+ *   - Return value: FCOO_OK (0) or a negative FCOO_E* code; the message of
+ *     the last error on the calling thread is fcoo_last_error().  No call
+ *     aborts or throws on bad input.
+ *   - A handle is not re-entrant (it owns scratch buffers): use one handle
+ *     per thread, or serialise calls on it.
+ */
+#ifndef FCOO_H
+#define FCOO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FCOO_OK = 0,
+    FCOO_EINVAL = -1,        /* null pointer, mode out of range, bad option value */
+    FCOO_ENOMEM = -2,        /* host or device allocation failed */
+    FCOO_EHIP = -3,          /* a HIP runtime call failed (message holds its text) */
+    FCOO_ENOTBUILT = -4,     /* operation on an (op, mode) that fcoo_build has not built */
+    FCOO_ERANGE = -5,        /* a coordinate is >= its dimension, or a size overflows */
+    FCOO_EUNSUPPORTED = -6   /* order outside [2, 8], R outside [1, 256], unknown dtype */
+};
+
+/* Operation classes (Table I): decide which modes are index / product modes. */
+enum fcoo_op {
+    FCOO_OP_MTTKRP = 0,      /* index mode = {mode}, product modes = all others        */
+    FCOO_OP_TTM = 1          /* index modes = all others, product mode = {mode}        */
+};
+
+/* Storage type of dense factor matrices read by the kernels. */
+enum fcoo_dtype {
+    FCOO_F32 = 0,            /* float32                                                */
+    FCOO_BF16 = 1            /* bfloat16 (upper 16 bits of a float32); FP32 accumulate */
+};
+
+typedef struct fcoo_tensor fcoo_tensor;   /* opaque; owned by the library */
+
+/* Build options.  A zero field selects the default. */
+typedef struct {
+    int threadlen;   /* nonzeros per partition: 8, 16, 32 or 64 (default 16).  One sf
+                        bit per partition (Sec. IV-B, Table II). */
+    int tile_nnz;    /* nonzeros per workgroup tile: a multiple of 256 and of
+                        threadlen (default 4096). */
+    int host_only;   /* 1: build the host arrays only (no device upload), e.g. to
+                        fcoo_export them on a machine without a GPU. */
+    int reserved;
+} fcoo_opts;
+
+/* Sizes of one built (op, mode). */
+typedef struct {
+    int64_t nnz;          /* Z */
+    int64_t nseg;         /* segments: non-empty slices (MTTKRP) or fibres (TTM) */
+    int64_t npart;        /* partitions P = ceil(Z / threadlen)                   */
+    int64_t ntiles;       /* ceil(Z / tile_nnz)                                   */
+    int64_t nfix;         /* segments finished by the carry fix-up pass           */
+    int64_t nempty;       /* MTTKRP: output rows with no nonzero (written as 0)   */
+    int64_t bytes_format; /* bytes of the F-COO arrays (pidx, val, bf, sf)        */
+    int64_t bytes_device; /* all device bytes held for this (op, mode)            */
+    int32_t threadlen;
+    int32_t tile_nnz;
+    int32_t order;
+    int32_t on_device;    /* 1 if uploaded                                        */
+} fcoo_info_t;
+
+/*
+ * fcoo_create -- copy a COO tensor into a new handle.
+ *   order   number of modes N, 2..8.
+ *   dims    host, N dimension sizes, each in [1, 2^31 - 1].
+ *   nnz     Z >= 0 (Z = 0 is valid: every result is zero).
+ *   idx     host, N pointers to host int32 arrays of Z 0-based coordinates.
+ *   vals    host, Z float32 values.  Repeated coordinates are kept as separate
+ *           nonzeros and add (COO semantics).
+ *   out     receives the handle; release it with fcoo_destroy.
+ * Errors: FCOO_EINVAL (null), FCOO_EUNSUPPORTED (order), FCOO_ERANGE (a
+ * coordinate outside [0, dims[m]) or a bad dimension), FCOO_ENOMEM.
+ */
+int fcoo_create(int order, const int64_t *dims, int64_t nnz, const int32_t *const *idx,
+                const float *vals, fcoo_tensor **out);
+
+/*
+ * fcoo_build -- build the F-COO form of the tensor for (op, mode) on the
+ * host and upload it once (Sec. IV-B; the paper prepares F-COO per mode on
+ * the host and transfers it once, Sec. IV-D).
+ *   The nonzeros are ordered by the index-mode tuple, then the product-mode
+ *   tuple (stable; ties keep input order).  Stored per nonzero: the
+ *   product-mode indices and the value.  bf: a parity bit per nonzero that
+ *   starts at 1 and toggles at each new segment (slice for MTTKRP, fibre for
+ *   TTM).  sf: one bit per partition of `threadlen` nonzeros, set iff a
+ *   segment starts inside it.  Per segment: its output row (MTTKRP) or its
+ *   fibre coordinates (TTM).  Per tile: the ordinal of the segment holding
+ *   its first nonzero.
+ *   opts may be NULL (defaults).  Rebuilding an (op, mode) replaces it.
+ *   Waits for the upload to finish before returning.
+ * Errors: FCOO_EINVAL, FCOO_ENOMEM, FCOO_EHIP.
+ */
+int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *stream);
+
+/* fcoo_info -- sizes of a built (op, mode).  Errors: FCOO_EINVAL, FCOO_ENOTBUILT. */
+int fcoo_info(const fcoo_tensor *t, int mode, int op, fcoo_info_t *info);
+
+/*
+ * fcoo_export -- host copies of a built (op, mode)'s arrays (any pointer may
+ * be NULL to skip it).  Sizes come from fcoo_info:
+ *   pidx      |product modes| pointers to Z int32 each, in ascending mode order
+ *   val       Z float32
+ *   bf        ceil(Z / 8) bytes, bit s of the stream at byte s>>3, bit s&7
+ *   sf        ceil(npart / 32) uint32 words, bit p at word p>>5, bit p&31
+ *   seg       MTTKRP: nseg int32 output rows (strictly increasing);
+ *             TTM: nseg x (N-1) int32 fibre coordinates, row-major, the
+ *             index modes in ascending order (lexicographically increasing)
+ *   tile_seg0 ntiles int32: ordinal of the segment holding nonzero t*tile_nnz
+ *   perm      Z int32: input position of the nonzero stored at position s
+ * Errors: FCOO_EINVAL, FCOO_ENOTBUILT.
+ */
+int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, float *val,
+                uint8_t *bf, uint32_t *sf, int32_t *seg, int32_t *tile_seg0, int32_t *perm);
+
+/*
+ * fcoo_spmttkrp -- M = X_(mode) (Khatri-Rao product of the other factors),
+ * computed over the nonzeros in one shot (Eq. 5 / Eq. 6):
+ *   M[i, r] = sum over nonzeros e with i_mode(e) = i of
+ *             val(e) * prod_{m != mode} A_m[i_m(e), r].
+ *   factors  host array of N device pointers; factors[m] is dims[m] x R of
+ *            `dtype`; factors[mode] is not read (may be NULL).
+ *   M        device, dims[mode] x R float32, written fully (rows of empty
+ *            slices are written as 0).  Must not alias a factor.
+ * Requires fcoo_build(mode, FCOO_OP_MTTKRP).  Deterministic: repeated calls
+ * give bitwise-identical results (no atomics).
+ * Errors: FCOO_EINVAL, FCOO_ENOTBUILT, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
+ */
+int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,
+                  float *M, void *stream);
+
+/*
+ * fcoo_spttm -- Y = X x_mode U (Eq. 3), semi-sparse result:
+ *   Y[g, :] = sum over nonzeros e of fibre g of val(e) * U[i_mode(e), :]
+ *   where fibre g is the g-th distinct tuple of the other modes' indices in
+ *   lexicographic order (fcoo_export's `seg`).  Structurally present fibres
+ *   are all listed, also when their sum cancels to zero.
+ *   U   device, dims[mode] x R of `dtype`.
+ *   Y   device, nseg x R float32, written fully.
+ * Requires fcoo_build(mode, FCOO_OP_TTM).
+ * Errors: as fcoo_spmttkrp.
+ */
+int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float *Y, void *stream);
+
+/*
+ * fcoo_spmttkrp_values -- fcoo_spmttkrp with the tensor's values replaced
+ * by `g` (device, Z float32 in the caller's input order of fcoo_create):
+ *   M[i, r] = sum_{e : i_mode(e) = i} g[e] prod_{m != mode} A_m[i_m(e), r].
+ * This is the adjoint of the CP model at the nonzeros (its gradient with
+ * respect to A_mode when g = dL/dxhat).
+ * Requires fcoo_build(mode, FCOO_OP_MTTKRP).  Errors: as fcoo_spmttkrp.
+ */
+int fcoo_spmttkrp_values(fcoo_tensor *t, int mode, const float *g, const void *const *factors,
+                         int dtype, int R, float *M, void *stream);
+
+/*
+ * fcoo_model_at_nnz -- CP model at the nonzeros:
+ *   xhat[e] = sum_r prod_m A_m[i_m(e), r], e in the caller's input order.
+ *   xhat  device, Z float32.  The first call uploads the coordinate list.
+ * Errors: FCOO_EINVAL, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
+ */
+int fcoo_model_at_nnz(fcoo_tensor *t, const void *const *factors, int dtype, int R, float *xhat,
+                      void *stream);
+
+/*
+ * fcoo_resid_spmttkrp -- fused gradient of the mean-squared error of the CP
+ * model at the nonzeros, L = (1 / 2Z) sum_e (xhat_e - x_e)^2, for one mode:
+ *   G[i, r] = (1/Z) sum_{e : i_mode(e) = i} (xhat_e - x_e) prod_{m != mode} A_m[i_m(e), r]
+ *   recomputing xhat_e from the factor rows (nothing per nonzero is stored).
+ *   G     device, dims[mode] x R float32, written fully.
+ *   loss  device double* or NULL; if given, receives L (computed in the same
+ *         pass, reduced deterministically).
+ * Requires fcoo_build(mode, FCOO_OP_MTTKRP).  Errors: as fcoo_spmttkrp.
+ */
+int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,
+                        float *G, double *loss, void *stream);
+
+/*
+ * fcoo_cp_als_iter -- one sweep of CP-ALS (Algorithm 1, N modes, Gauss-Seidel):
+ * for n = 0..N-1: M = SpMTTKRP_n; V = Hadamard product of the Grams G_m,
+ * m != n (float64); A_n = M V^-1 (float64 Cholesky; symmetric-eigen
+ * pseudo-inverse when V is not positive definite); lambda = column 2-norms
+ * of A_n; A_n columns divided by lambda (zero columns left zero); A_n stored
+ * as `dtype` (round to nearest even); G_n = A_n^T A_n of the stored values.
+ * Then fit = 1 - sqrt(max(0, |X|^2 + |Xhat|^2 - 2 <X, Xhat>)) / |X|.
+ *   factors  host array of N device pointers, in/out, dims[m] x R of `dtype`.
+ *   lambda   device, R float64 (out: the norms of the last mode).
+ *   grams    device, N x R x R float64, in/out: G_m = A_m^T A_m.  Set
+ *            `grams_valid` = 0 to have them computed from the factors first.
+ *   fit      host double* (out); the call waits for it.
+ *   used_pinv host int* or NULL (out): bit n set if mode n used the pseudo-inverse.
+ * Requires fcoo_build(n, FCOO_OP_MTTKRP) for every mode n.
+ * Errors: FCOO_EINVAL, FCOO_ENOTBUILT, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
+ */
+int fcoo_cp_als_iter(fcoo_tensor *t, void *const *factors, int dtype, int R, double *lambda,
+                     double *grams, int grams_valid, double *fit, int *used_pinv, void *stream);
+
+/*
+ * fcoo_gram -- G = A^T A (float64 R x R, device) of a dims[mode] x R factor
+ * (device, `dtype`): matrix-core (MFMA) products per row block, float64 sum
+ * across blocks.  Errors: FCOO_EINVAL, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
+ */
+int fcoo_gram(fcoo_tensor *t, int mode, const void *A, int dtype, int R, double *G, void *stream);
+
+/*
+ * fcoo_set_tile_events -- instrumentation for callers that time the tile
+ * kernel alone.  While `before` and `after` (hipEvent_t values passed as
+ * void*, created and owned by the caller) are non-NULL, every SpMTTKRP /
+ * SpTTM / value-replaced / residual call on this handle records `before` on
+ * its stream immediately before its tile kernel and `after` immediately
+ * after it.  Passing NULL, NULL switches recording off.  Changes no result.
+ * Errors: FCOO_EINVAL (null handle, or exactly one event NULL).
+ */
+int fcoo_set_tile_events(fcoo_tensor *t, void *before, void *after);
+
+/* fcoo_destroy -- free the handle and every device buffer it owns (NULL is ignored). */
+void fcoo_destroy(fcoo_tensor *t);
+
+/* fcoo_last_error -- message of the calling thread's last failed call ("" if none). */
+const char *fcoo_last_error(void);
+
+/* fcoo_version -- ABI version (major * 100 + minor). */
+int fcoo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCOO_H */

@@ -1,0 +1,676 @@
+// Host side of the F-COO library: the handle, the per-(op, mode) F-COO
+// build (mode sort, bf / sf flags, per-segment and per-tile indexing, the
+// carry fix-up list), the one-time upload, export, and argument checking of
+// the C ABI.  F-COO itself is defined in Sec. IV-B; the build runs on the
+// host once per mode and is uploaded once (Sec. IV-D, "complete tensor-based
+// algorithms").
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <thread>
+
+#include "fcoo_internal.h"
+
+namespace fcoo {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return fail(FCOO_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(FCOO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+// ---------------------------------------------------------------------------
+// small parallel helpers (std::thread; the host build is a one-time cost)
+// ---------------------------------------------------------------------------
+static int host_threads()
+{
+    const char *e = getenv("FCOO_HOST_THREADS");
+    int n = e ? atoi(e) : (int)std::thread::hardware_concurrency();
+    if (n < 1) n = 1;
+    if (n > 32) n = 32;
+    return n;
+}
+
+template <class F>
+static void parallel_chunks(int64_t n, int T, F fn)
+{
+    if (T <= 1 || n < 65536) {
+        fn(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t)
+        th.emplace_back([=]() { fn(t, n * t / T, n * (t + 1) / T); });
+    for (auto &x : th) x.join();
+}
+
+// Stable LSD radix sort of (key, id) pairs, 11-bit digits, `bits` significant
+// key bits.  Ties keep their incoming order.
+static void radix_sort(std::vector<uint64_t> &k, std::vector<uint32_t> &v, int bits, int T)
+{
+    const int64_t n = (int64_t)k.size();
+    if (n < 2 || bits <= 0) return;
+    constexpr int DB = 11, NB = 1 << DB;
+    std::vector<uint64_t> k2(n);
+    std::vector<uint32_t> v2(n);
+    if (n < 65536) T = 1;
+    std::vector<int64_t> hist((size_t)T * NB);
+    for (int shift = 0; shift < bits; shift += DB) {
+        std::fill(hist.begin(), hist.end(), 0);
+        parallel_chunks(n, T, [&](int t, int64_t b, int64_t e) {
+            int64_t *h = hist.data() + (size_t)t * NB;
+            for (int64_t i = b; i < e; ++i) h[(k[i] >> shift) & (NB - 1)]++;
+        });
+        bool trivial = false;
+        for (int d = 0; d < NB && !trivial; ++d) {
+            int64_t c = 0;
+            for (int t = 0; t < T; ++t) c += hist[(size_t)t * NB + d];
+            if (c == n) trivial = true;
+            else if (c) break;
+        }
+        if (trivial) continue;
+        int64_t run = 0;
+        for (int d = 0; d < NB; ++d)
+            for (int t = 0; t < T; ++t) {
+                int64_t c = hist[(size_t)t * NB + d];
+                hist[(size_t)t * NB + d] = run;
+                run += c;
+            }
+        parallel_chunks(n, T, [&](int t, int64_t b, int64_t e) {
+            int64_t *h = hist.data() + (size_t)t * NB;
+            for (int64_t i = b; i < e; ++i) {
+                int64_t p = h[(k[i] >> shift) & (NB - 1)]++;
+                k2[p] = k[i];
+                v2[p] = v[i];
+            }
+        });
+        k.swap(k2);
+        v.swap(v2);
+    }
+}
+
+static int bit_width(int64_t d)  // bits to hold 0..d-1
+{
+    int b = 0;
+    while (b < 63 && ((int64_t)1 << b) < d) ++b;
+    return b;
+}
+
+int64_t Built::format_bytes() const
+{
+    int64_t s = 0;
+    for (auto &p : pidx) s += (int64_t)p.size() * 4;
+    return s + (int64_t)val.size() * 4 + (int64_t)bf.size() + (int64_t)sf.size() * 4;
+}
+
+void Built::free_device()
+{
+    for (auto &p : d_pidx) { if (p) hipFree(p); p = nullptr; }
+    void *ptrs[] = {d_val, d_bf, d_sf, d_seg_row, d_tile_seg0, d_perm, d_fix, d_empty, d_carry,
+                    d_gperm, d_partial};
+    for (void *p : ptrs) if (p) hipFree(p);
+    d_val = nullptr; d_bf = nullptr; d_sf = nullptr; d_seg_row = nullptr; d_tile_seg0 = nullptr;
+    d_perm = nullptr; d_fix = nullptr; d_empty = nullptr; d_carry = nullptr; d_gperm = nullptr;
+    d_partial = nullptr;
+    carry_cap = 0; partial_cap = 0; device_bytes = 0;
+    on_device = false;
+}
+
+void Workspace::free_all()
+{
+    if (M) hipFree(M);
+    if (dbl) hipFree(dbl);
+    if (flags) hipFree(flags);
+    if (host_pinned) hipHostFree(host_pinned);
+    M = nullptr; dbl = nullptr; flags = nullptr; host_pinned = nullptr;
+    M_cap = dbl_cap = 0;
+}
+
+// Grow a device scratch buffer.  The old buffer may still be read by work
+// queued on `s`, so the stream is drained before it is released.
+int ensure_device_floats(float **p, int64_t *cap, int64_t need, hipStream_t s)
+{
+    if (need <= *cap) return FCOO_OK;
+    if (*p) {
+        FCOO_HIP(hipStreamSynchronize(s));
+        FCOO_HIP(hipFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    FCOO_HIP(hipMalloc((void **)p, (size_t)need * sizeof(float)));
+    *cap = need;
+    return FCOO_OK;
+}
+
+int ensure_device_doubles(double **p, int64_t *cap, int64_t need, hipStream_t s)
+{
+    if (need <= *cap) return FCOO_OK;
+    if (*p) {
+        FCOO_HIP(hipStreamSynchronize(s));
+        FCOO_HIP(hipFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    FCOO_HIP(hipMalloc((void **)p, (size_t)need * sizeof(double)));
+    *cap = need;
+    return FCOO_OK;
+}
+
+template <class T>
+static int upload(T **dst, const T *src, int64_t n, int64_t pad_elems, hipStream_t s, int64_t *acct)
+{
+    const size_t bytes = (size_t)(n + pad_elems) * sizeof(T);
+    FCOO_HIP(hipMalloc((void **)dst, bytes ? bytes : sizeof(T)));
+    if (pad_elems) FCOO_HIP(hipMemsetAsync(*dst, 0, bytes, s));
+    if (n) FCOO_HIP(hipMemcpyAsync(*dst, src, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
+    *acct += (int64_t)bytes;
+    return FCOO_OK;
+}
+
+int upload_coo(fcoo_tensor *t, hipStream_t s)
+{
+    if (t->coo_on_device) return FCOO_OK;
+    int64_t acct = 0;
+    for (int m = 0; m < t->order; ++m) {
+        int rc = upload(&t->d_coo[m], t->idx[m].data(), t->nnz, 0, s, &acct);
+        if (rc) return rc;
+    }
+    int rc = upload(&t->d_coo_val, t->vals.data(), t->nnz, 0, s, &acct);
+    if (rc) return rc;
+    FCOO_HIP(hipStreamSynchronize(s));
+    t->coo_on_device = true;
+    return FCOO_OK;
+}
+
+int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R)
+{
+    if (!factors) return fail(FCOO_EINVAL, "factors is NULL");
+    if (dtype != FCOO_F32 && dtype != FCOO_BF16) return fail(FCOO_EUNSUPPORTED, "unknown dtype %d", dtype);
+    if (R < 1 || R > kMaxR) return fail(FCOO_EUNSUPPORTED, "R = %d outside [1, %d]", R, kMaxR);
+    for (int m = 0; m < t->order; ++m)
+        if (m != skip_mode && !factors[m]) return fail(FCOO_EINVAL, "factors[%d] is NULL", m);
+    return FCOO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the F-COO build for one (op, mode)
+// ---------------------------------------------------------------------------
+static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz)
+{
+    const int N = t->order;
+    const int64_t Z = t->nnz;
+    const int T = host_threads();
+    b = Built();
+    b.op = op; b.mode = mode; b.threadlen = threadlen; b.tile_nnz = tile_nnz; b.nnz = Z;
+    for (int m = 0; m < N; ++m) {
+        if (m == mode) continue;
+        if (op == FCOO_OP_MTTKRP) b.pmodes.push_back(m); else b.imodes.push_back(m);
+    }
+    if (op == FCOO_OP_MTTKRP) b.imodes.insert(b.imodes.begin(), mode); else b.pmodes.push_back(mode);
+
+    // 1. stable lexicographic order of (index-mode tuple, product-mode tuple)
+    std::vector<int> order_modes(b.imodes);
+    order_modes.insert(order_modes.end(), b.pmodes.begin(), b.pmodes.end());
+    int total_bits = 0, pbits = 0;
+    for (int m : b.imodes) total_bits += bit_width(t->dims[m]);
+    for (int m : b.pmodes) { int w = bit_width(t->dims[m]); total_bits += w; pbits += w; }
+    std::vector<uint32_t> perm(Z);
+    std::vector<uint64_t> key;
+    const bool packed = total_bits <= 64;
+    if (packed) {
+        key.resize(Z);
+        parallel_chunks(Z, T, [&](int, int64_t lo, int64_t hi) {
+            for (int64_t e = lo; e < hi; ++e) {
+                uint64_t k = 0;
+                for (int m : order_modes) k = (bit_width(t->dims[m]) ? (k << bit_width(t->dims[m])) : k) | (uint64_t)t->idx[m][e];
+                key[e] = k;
+                perm[e] = (uint32_t)e;
+            }
+        });
+        radix_sort(key, perm, total_bits, T);
+    } else {
+        for (int64_t e = 0; e < Z; ++e) perm[e] = (uint32_t)e;
+        std::stable_sort(perm.begin(), perm.end(), [&](uint32_t x, uint32_t y) {
+            for (int m : order_modes) {
+                int32_t a = t->idx[m][x], c = t->idx[m][y];
+                if (a != c) return a < c;
+            }
+            return false;
+        });
+    }
+
+    // 2. per-nonzero arrays in sorted order, and segment heads
+    b.perm.resize(Z);
+    b.val.resize(Z);
+    b.pidx.assign(b.pmodes.size(), std::vector<int32_t>(Z));
+    std::vector<uint8_t> head(Z);
+    parallel_chunks(Z, T, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t s = lo; s < hi; ++s) {
+            const uint32_t e = perm[s];
+            b.perm[s] = (int32_t)e;
+            b.val[s] = t->vals[e];
+            for (size_t q = 0; q < b.pmodes.size(); ++q) b.pidx[q][s] = t->idx[b.pmodes[q]][e];
+            bool h = (s == 0);
+            if (!h) {
+                if (packed) h = (key[s] >> pbits) != (key[s - 1] >> pbits);
+                else
+                    for (int m : b.imodes)
+                        if (t->idx[m][e] != t->idx[m][perm[s - 1]]) { h = true; break; }
+            }
+            head[s] = h;
+        }
+    });
+    key.clear(); key.shrink_to_fit();
+
+    // 3. bf (parity toggled at each head, starting at 1), sf, segments, tiles
+    const int64_t P = (Z + threadlen - 1) / threadlen;
+    const int64_t ntiles = (Z + tile_nnz - 1) / tile_nnz;
+    b.npart = P; b.ntiles = ntiles;
+    b.bf.assign((Z + 7) / 8, 0);
+    b.sf.assign((P + 31) / 32, 0);
+    b.tile_seg0.resize(ntiles);
+    std::vector<int64_t> seg_start;  // position of each head
+    std::vector<int64_t> heads_before_tile(ntiles + 1, 0);
+    std::vector<uint8_t> tile_has_head(ntiles, 0);
+    int64_t cnt = 0;
+    for (int64_t s = 0; s < Z; ++s) {
+        if (s % tile_nnz == 0) heads_before_tile[s / tile_nnz] = cnt;
+        if (head[s]) {
+            ++cnt;
+            seg_start.push_back(s);
+            b.sf[(s / threadlen) >> 5] |= 1u << ((s / threadlen) & 31);
+            tile_has_head[s / tile_nnz] = 1;
+        }
+        if (cnt & 1) b.bf[s >> 3] |= (uint8_t)(1u << (s & 7));
+        if (s % tile_nnz == 0) b.tile_seg0[s / tile_nnz] = (int32_t)(cnt - 1);
+    }
+    heads_before_tile[ntiles] = cnt;
+    b.nseg = cnt;
+    const int nim = (int)b.imodes.size();
+    b.seg.resize((size_t)cnt * nim);
+    for (int64_t g = 0; g < cnt; ++g) {
+        const uint32_t e = perm[seg_start[g]];
+        for (int q = 0; q < nim; ++q) b.seg[(size_t)g * nim + q] = t->idx[b.imodes[q]][e];
+    }
+
+    // 4. carry fix-up list: a segment that is still open at the end of a tile
+    //    is finished by the first head of a later tile (or by the end of the
+    //    tensor).  Entry (b, a, row): tiles a+1 .. b-1 hold no head, tile a
+    //    holds the segment's start.  The segment closed at tile b's first
+    //    head is the last one that starts before tile b.
+    auto out_row = [&](int64_t g) -> int32_t {
+        return op == FCOO_OP_MTTKRP ? b.seg[(size_t)g] : (int32_t)g;
+    };
+    int64_t last = -1;
+    for (int64_t tb = 0; tb < ntiles; ++tb) {
+        if (!tile_has_head[tb]) continue;
+        if (tb >= 1) {
+            const int64_t g = heads_before_tile[tb] - 1;
+            b.fix.push_back((int32_t)tb);
+            b.fix.push_back((int32_t)last);
+            b.fix.push_back(out_row(g));
+        }
+        last = tb;
+    }
+    if (Z > 0) {
+        b.fix.push_back((int32_t)ntiles);
+        b.fix.push_back((int32_t)last);
+        b.fix.push_back(out_row(cnt - 1));
+    }
+
+    // 5. output rows of MTTKRP that no nonzero touches
+    if (op == FCOO_OP_MTTKRP) {
+        std::vector<uint8_t> present(t->dims[mode], 0);
+        for (int64_t g = 0; g < cnt; ++g) present[b.seg[g]] = 1;
+        for (int64_t i = 0; i < t->dims[mode]; ++i)
+            if (!present[i]) b.empty_rows.push_back((int32_t)i);
+    }
+    b.built = true;
+    return FCOO_OK;
+}
+
+static int build_device(Built &b, hipStream_t s)
+{
+    int64_t acct = 0;
+    int rc;
+    for (size_t q = 0; q < b.pidx.size(); ++q)
+        if ((rc = upload(&b.d_pidx[q], b.pidx[q].data(), b.nnz, 0, s, &acct))) return rc;
+    if ((rc = upload(&b.d_val, b.val.data(), b.nnz, 0, s, &acct))) return rc;
+    {   // bit stream as uint32 words plus two zero words (64-bit windows never read past it)
+        const int64_t words = (b.nnz + 31) / 32;
+        std::vector<uint32_t> w(words, 0);
+        if (!b.bf.empty()) memcpy(w.data(), b.bf.data(), b.bf.size());
+        if ((rc = upload(&b.d_bf, w.data(), words, 2, s, &acct))) return rc;
+        FCOO_HIP(hipStreamSynchronize(s));
+    }
+    if ((rc = upload(&b.d_sf, b.sf.data(), (int64_t)b.sf.size(), 1, s, &acct))) return rc;
+    if (b.op == FCOO_OP_MTTKRP)
+        if ((rc = upload(&b.d_seg_row, b.seg.data(), b.nseg, 1, s, &acct))) return rc;
+    if ((rc = upload(&b.d_tile_seg0, b.tile_seg0.data(), b.ntiles, 1, s, &acct))) return rc;
+    if ((rc = upload(&b.d_perm, b.perm.data(), b.nnz, 0, s, &acct))) return rc;
+    if ((rc = upload(&b.d_fix, b.fix.data(), (int64_t)b.fix.size(), 3, s, &acct))) return rc;
+    if ((rc = upload(&b.d_empty, b.empty_rows.data(), (int64_t)b.empty_rows.size(), 1, s, &acct)))
+        return rc;
+    FCOO_HIP(hipStreamSynchronize(s));
+    b.device_bytes = acct;
+    b.on_device = true;
+    return FCOO_OK;
+}
+
+static Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device)
+{
+    if (!t) { fail(FCOO_EINVAL, "null handle"); return nullptr; }
+    if (mode < 0 || mode >= t->order) { fail(FCOO_EINVAL, "mode %d out of range", mode); return nullptr; }
+    if (op != FCOO_OP_MTTKRP && op != FCOO_OP_TTM) { fail(FCOO_EINVAL, "unknown op %d", op); return nullptr; }
+    Built &b = t->b[op][mode];
+    if (!b.built || (need_device && !b.on_device)) {
+        fail(FCOO_ENOTBUILT, "(op %d, mode %d) is not built%s", op, mode,
+             b.built ? " on the device" : "");
+        return nullptr;
+    }
+    return &b;
+}
+
+Built *get_built_public(fcoo_tensor *t, int mode, int op, bool need_device)
+{
+    return get_built(t, mode, op, need_device);
+}
+
+}  // namespace fcoo
+
+using namespace fcoo;
+
+extern "C" {
+
+int fcoo_version(void) { return 100; }
+
+const char *fcoo_last_error(void) { return fcoo::g_err.c_str(); }
+
+int fcoo_create(int order, const int64_t *dims, int64_t nnz, const int32_t *const *idx,
+                const float *vals, fcoo_tensor **out)
+{
+    clear_error();
+    if (!out) return fail(FCOO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (order < 2 || order > kMaxOrder) return fail(FCOO_EUNSUPPORTED, "order %d outside [2, 8]", order);
+    if (!dims) return fail(FCOO_EINVAL, "dims is NULL");
+    if (nnz < 0) return fail(FCOO_EINVAL, "nnz < 0");
+    if (nnz > 0 && (!idx || !vals)) return fail(FCOO_EINVAL, "idx or vals is NULL");
+    if (nnz > (int64_t)INT32_MAX) return fail(FCOO_ERANGE, "nnz %lld exceeds 2^31 - 1", (long long)nnz);
+    for (int m = 0; m < order; ++m) {
+        if (dims[m] < 1 || dims[m] > (int64_t)INT32_MAX)
+            return fail(FCOO_ERANGE, "dims[%d] = %lld outside [1, 2^31 - 1]", m, (long long)dims[m]);
+        if (nnz > 0 && !idx[m]) return fail(FCOO_EINVAL, "idx[%d] is NULL", m);
+    }
+    fcoo_tensor *t = new (std::nothrow) fcoo_tensor();
+    if (!t) return fail(FCOO_ENOMEM, "handle");
+    try {
+        t->order = order;
+        t->nnz = nnz;
+        for (int m = 0; m < order; ++m) {
+            t->dims[m] = dims[m];
+            t->idx[m].assign(idx ? idx[m] : nullptr, idx ? idx[m] + nnz : nullptr);
+        }
+        t->vals.assign(vals, vals + nnz);
+    } catch (const std::bad_alloc &) {
+        delete t;
+        return fail(FCOO_ENOMEM, "copying %lld nonzeros", (long long)nnz);
+    }
+    for (int m = 0; m < order; ++m) {
+        const int32_t *c = t->idx[m].data();
+        const int64_t d = dims[m];
+        for (int64_t e = 0; e < nnz; ++e)
+            if (c[e] < 0 || (int64_t)c[e] >= d) {
+                int rc = fail(FCOO_ERANGE, "idx[%d][%lld] = %d outside [0, %lld)", m, (long long)e,
+                              c[e], (long long)d);
+                delete t;
+                return rc;
+            }
+    }
+    double s = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) s += (double)t->vals[e] * (double)t->vals[e];
+    t->normX2 = s;
+    *out = t;
+    return FCOO_OK;
+}
+
+int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *stream)
+{
+    clear_error();
+    if (!t) return fail(FCOO_EINVAL, "null handle");
+    if (mode < 0 || mode >= t->order) return fail(FCOO_EINVAL, "mode %d out of range", mode);
+    if (op != FCOO_OP_MTTKRP && op != FCOO_OP_TTM) return fail(FCOO_EINVAL, "unknown op %d", op);
+    int threadlen = opts && opts->threadlen ? opts->threadlen : 16;
+    int tile_nnz = opts && opts->tile_nnz ? opts->tile_nnz : 4096;
+    const bool host_only = opts && opts->host_only;
+    if (threadlen != 8 && threadlen != 16 && threadlen != 32 && threadlen != 64)
+        return fail(FCOO_EINVAL, "threadlen %d not in {8, 16, 32, 64}", threadlen);
+    if (tile_nnz <= 0 || tile_nnz % 256 || tile_nnz % threadlen || tile_nnz > (1 << 20))
+        return fail(FCOO_EINVAL, "tile_nnz %d must be a positive multiple of 256 and threadlen, <= 2^20",
+                    tile_nnz);
+    Built &b = t->b[op][mode];
+    b.free_device();
+    int rc;
+    try {
+        rc = build_host(t, b, mode, op, threadlen, tile_nnz);
+    } catch (const std::bad_alloc &) {
+        b = Built();
+        return fail(FCOO_ENOMEM, "host build");
+    }
+    if (rc) return rc;
+    if (host_only) return FCOO_OK;
+    rc = build_device(b, (hipStream_t)stream);
+    if (rc) { b.free_device(); return rc; }
+    return FCOO_OK;
+}
+
+int fcoo_info(const fcoo_tensor *t, int mode, int op, fcoo_info_t *info)
+{
+    clear_error();
+    if (!info) return fail(FCOO_EINVAL, "info is NULL");
+    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false);
+    if (!b) return FCOO_ENOTBUILT == 0 ? 0 : (t ? FCOO_ENOTBUILT : FCOO_EINVAL);
+    info->nnz = b->nnz;
+    info->nseg = b->nseg;
+    info->npart = b->npart;
+    info->ntiles = b->ntiles;
+    info->nfix = b->nfix();
+    info->nempty = (int64_t)b->empty_rows.size();
+    info->bytes_format = b->format_bytes();
+    info->bytes_device = b->device_bytes;
+    info->threadlen = b->threadlen;
+    info->tile_nnz = b->tile_nnz;
+    info->order = t->order;
+    info->on_device = b->on_device ? 1 : 0;
+    return FCOO_OK;
+}
+
+int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, float *val,
+                uint8_t *bf, uint32_t *sf, int32_t *seg, int32_t *tile_seg0, int32_t *perm)
+{
+    clear_error();
+    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    if (pidx)
+        for (size_t q = 0; q < b->pidx.size(); ++q)
+            if (pidx[q]) memcpy(pidx[q], b->pidx[q].data(), b->pidx[q].size() * 4);
+    if (val) memcpy(val, b->val.data(), b->val.size() * 4);
+    if (bf) memcpy(bf, b->bf.data(), b->bf.size());
+    if (sf) memcpy(sf, b->sf.data(), b->sf.size() * 4);
+    if (seg) memcpy(seg, b->seg.data(), b->seg.size() * 4);
+    if (tile_seg0) memcpy(tile_seg0, b->tile_seg0.data(), b->tile_seg0.size() * 4);
+    if (perm) memcpy(perm, b->perm.data(), b->perm.size() * 4);
+    return FCOO_OK;
+}
+
+void fcoo_destroy(fcoo_tensor *t)
+{
+    if (!t) return;
+    for (auto &row : t->b)
+        for (auto &b : row) b.free_device();
+    for (auto &p : t->d_coo) if (p) hipFree(p);
+    if (t->d_coo_val) hipFree(t->d_coo_val);
+    t->ws.free_all();
+    delete t;
+}
+
+// ---------------------------------------------------------------------------
+// sparse operations: argument checks, then the HIP launchers
+// ---------------------------------------------------------------------------
+int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R, float *M,
+                  void *stream)
+{
+    clear_error();
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc = check_factors(t, mode, factors, dtype, R);
+    if (rc) return rc;
+    if (!M) return fail(FCOO_EINVAL, "M is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    TileProblem p{};
+    p.b = b;
+    for (size_t q = 0; q < b->pmodes.size(); ++q) p.fac[q] = factors[b->pmodes[q]];
+    p.vals = b->d_val;
+    p.dtype = dtype;
+    p.R = R;
+    p.out = M;
+    if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
+    p.carry = b->d_carry;
+    p.ev_before = t->ev_before;
+    p.ev_after = t->ev_after;
+    return launch_segmented(p, s, false);
+}
+
+int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float *Y, void *stream)
+{
+    clear_error();
+    Built *b = get_built(t, mode, FCOO_OP_TTM, true);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    if ((!U && b->nnz) || (!Y && b->nseg)) return fail(FCOO_EINVAL, "U or Y is NULL");
+    if (dtype != FCOO_F32 && dtype != FCOO_BF16) return fail(FCOO_EUNSUPPORTED, "unknown dtype %d", dtype);
+    if (R < 1 || R > kMaxR) return fail(FCOO_EUNSUPPORTED, "R = %d outside [1, %d]", R, kMaxR);
+    hipStream_t s = (hipStream_t)stream;
+    TileProblem p{};
+    p.b = b;
+    p.fac[0] = U;
+    p.vals = b->d_val;
+    p.dtype = dtype;
+    p.R = R;
+    p.out = Y;
+    int rc;
+    if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
+    p.carry = b->d_carry;
+    p.ev_before = t->ev_before;
+    p.ev_after = t->ev_after;
+    return launch_segmented(p, s, false);
+}
+
+int fcoo_spmttkrp_values(fcoo_tensor *t, int mode, const float *g, const void *const *factors,
+                         int dtype, int R, float *M, void *stream)
+{
+    clear_error();
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc = check_factors(t, mode, factors, dtype, R);
+    if (rc) return rc;
+    if (!M || (!g && b->nnz)) return fail(FCOO_EINVAL, "M or g is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t cap = b->d_gperm ? b->nnz : 0;
+    if (!b->d_gperm && b->nnz) {
+        if ((rc = ensure_device_floats(&b->d_gperm, &cap, b->nnz, s))) return rc;
+    }
+    if (b->nnz && (rc = launch_permute_values(*b, g, b->d_gperm, s))) return rc;
+    TileProblem p{};
+    p.b = b;
+    for (size_t q = 0; q < b->pmodes.size(); ++q) p.fac[q] = factors[b->pmodes[q]];
+    p.vals = b->d_gperm;
+    p.dtype = dtype;
+    p.R = R;
+    p.out = M;
+    if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
+    p.carry = b->d_carry;
+    p.ev_before = t->ev_before;
+    p.ev_after = t->ev_after;
+    return launch_segmented(p, s, false);
+}
+
+int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,
+                        float *G, double *loss, void *stream)
+{
+    clear_error();
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc = check_factors(t, -1, factors, dtype, R);
+    if (rc) return rc;
+    if (!G) return fail(FCOO_EINVAL, "G is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    TileProblem p{};
+    p.b = b;
+    for (size_t q = 0; q < b->pmodes.size(); ++q) p.fac[q] = factors[b->pmodes[q]];
+    p.vals = b->d_val;
+    p.dtype = dtype;
+    p.R = R;
+    p.out = G;
+    p.own = factors[mode];
+    p.inv_nnz = b->nnz ? (float)(1.0 / (double)b->nnz) : 0.f;
+    if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
+    p.carry = b->d_carry;
+    if (loss) {
+        if ((rc = ensure_device_doubles(&b->d_partial, &b->partial_cap, b->ntiles + 1, s))) return rc;
+        p.partial = b->d_partial;
+    }
+    p.ev_before = t->ev_before;
+    p.ev_after = t->ev_after;
+    if ((rc = launch_segmented(p, s, true))) return rc;
+    if (loss) return launch_reduce_partials(b->d_partial, b->ntiles,
+                                            b->nnz ? 0.5 / (double)b->nnz : 0.0, loss, s);
+    return FCOO_OK;
+}
+
+int fcoo_set_tile_events(fcoo_tensor *t, void *before, void *after)
+{
+    clear_error();
+    if (!t) return fail(FCOO_EINVAL, "null handle");
+    if ((before == nullptr) != (after == nullptr)) return fail(FCOO_EINVAL, "give both events or neither");
+    t->ev_before = (hipEvent_t)before;
+    t->ev_after = (hipEvent_t)after;
+    return FCOO_OK;
+}
+
+int fcoo_model_at_nnz(fcoo_tensor *t, const void *const *factors, int dtype, int R, float *xhat,
+                      void *stream)
+{
+    clear_error();
+    if (!t) return fail(FCOO_EINVAL, "null handle");
+    int rc = check_factors(t, -1, factors, dtype, R);
+    if (rc) return rc;
+    if (!xhat && t->nnz) return fail(FCOO_EINVAL, "xhat is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = upload_coo(t, s))) return rc;
+    return launch_model(t, factors, dtype, R, xhat, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Internal declarations shared by the host builder and the HIP launchers.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fcoo.h"
+
+namespace fcoo {
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxR = 256;
+constexpr int kBlock = 256;        // threads per workgroup of the tile kernels (4 waves)
+
+// error reporting (thread-local message, negative code returned)
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+#define FCOO_HIP(call)                                  \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return ::fcoo::hip_fail(e_, #call); \
+    } while (0)
+
+// One (op, mode) F-COO build: host arrays (kept for export) and device copies.
+struct Built {
+    bool built = false;
+    bool on_device = false;
+    int op = 0, mode = 0, threadlen = 0, tile_nnz = 0;
+    int64_t nnz = 0, nseg = 0, npart = 0, ntiles = 0;
+    std::vector<int> imodes, pmodes;
+
+    // F-COO arrays (Sec. IV-B) and per-segment / per-tile indexing
+    std::vector<std::vector<int32_t>> pidx;   // |pmodes| x Z
+    std::vector<float> val;                   // Z
+    std::vector<uint8_t> bf;                  // ceil(Z/8)
+    std::vector<uint32_t> sf;                 // ceil(P/32)
+    std::vector<int32_t> seg;                 // MTTKRP: nseg rows; TTM: nseg x (N-1)
+    std::vector<int32_t> tile_seg0;           // ntiles
+    std::vector<int32_t> perm;                // Z: sorted position -> input position
+
+    // carry fix-up list: (closing tile b, chain start tile a, output row) per entry
+    std::vector<int32_t> fix;
+    std::vector<int32_t> empty_rows;          // MTTKRP rows with no nonzero
+
+    // device copies
+    int32_t *d_pidx[kMaxOrder] = {};
+    float *d_val = nullptr;
+    uint32_t *d_bf = nullptr;                 // bit stream as uint32 words, +2 zero words
+    uint32_t *d_sf = nullptr;
+    int32_t *d_seg_row = nullptr;             // MTTKRP only
+    int32_t *d_tile_seg0 = nullptr;
+    int32_t *d_perm = nullptr;
+    int32_t *d_fix = nullptr;
+    int32_t *d_empty = nullptr;
+    int64_t device_bytes = 0;
+
+    // scratch owned by this build, grown on demand
+    float *d_carry = nullptr;                 // 2 x ntiles x R floats
+    int64_t carry_cap = 0;                    // floats
+    float *d_gperm = nullptr;                 // Z floats (values in stored order)
+    double *d_partial = nullptr;              // per-tile float64 partial sums
+    int64_t partial_cap = 0;
+
+    int64_t nfix() const { return (int64_t)fix.size() / 3; }
+    int64_t format_bytes() const;
+    void free_device();
+};
+
+// Scratch for CP-ALS and small reductions, owned by the handle.
+struct Workspace {
+    float *M = nullptr;          int64_t M_cap = 0;      // floats
+    double *dbl = nullptr;       int64_t dbl_cap = 0;    // doubles
+    int *flags = nullptr;                               // device ints (pinv flags)
+    double *host_pinned = nullptr;                      // fit readback
+    void free_all();
+};
+
+}  // namespace fcoo
+
+struct fcoo_tensor {
+    int order = 0;
+    int64_t dims[fcoo::kMaxOrder] = {};
+    int64_t nnz = 0;
+    std::vector<int32_t> idx[fcoo::kMaxOrder];
+    std::vector<float> vals;
+    double normX2 = 0.0;                         // sum of squared values (float64)
+    fcoo::Built b[2][fcoo::kMaxOrder];
+
+    // coordinate list on the device (model at the nonzeros), uploaded on first use
+    int32_t *d_coo[fcoo::kMaxOrder] = {};
+    float *d_coo_val = nullptr;
+    bool coo_on_device = false;
+
+    fcoo::Workspace ws;
+
+    // optional events recorded around each tile kernel (caller-owned)
+    hipEvent_t ev_before = nullptr, ev_after = nullptr;
+};
+
+namespace fcoo {
+
+// helpers implemented in fcoo_host.cpp
+int ensure_device_floats(float **p, int64_t *cap, int64_t need, hipStream_t s);
+int ensure_device_doubles(double **p, int64_t *cap, int64_t need, hipStream_t s);
+int upload_coo(fcoo_tensor *t, hipStream_t s);
+int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
+
+// launchers implemented in the .hip files (return FCOO_OK or an error code)
+struct TileProblem {
+    const Built *b;
+    const void *fac[kMaxOrder];      // per product mode q: factor base pointer
+    const float *vals;               // values in stored order (b->d_val or a permuted copy)
+    int dtype;
+    int R;
+    float *out;                      // output rows, leading dimension R
+    float *carry;                    // 2 x ntiles x R
+    // fused MSE residual (resid_spmttkrp)
+    const void *own = nullptr;       // factor of the index mode (dims[mode] x R)
+    float inv_nnz = 0.f;
+    double *partial = nullptr;       // per-tile partial losses (ntiles) or null
+    hipEvent_t ev_before = nullptr;  // recorded around the tile kernel when set
+    hipEvent_t ev_after = nullptr;
+};
+int launch_segmented(const TileProblem &p, hipStream_t s, bool resid);
+int launch_permute_values(const Built &b, const float *g, float *out, hipStream_t s);
+int launch_reduce_partials(const double *partial, int64_t n, double scale, double *out, hipStream_t s);
+int launch_model(const fcoo_tensor *t, const void *const *factors, int dtype, int R, float *xhat,
+                 hipStream_t s);
+
+}  // namespace fcoo

@@ -1,0 +1,259 @@
+// Launch plans of the segmented F-COO operations, the carry fix-up, empty
+// rows, value permutation, deterministic float64 reductions and the CP
+// model at the nonzeros.
+#include "fcoo_internal.h"
+#include "fcoo_seg_dispatch.h"
+
+namespace fcoo {
+
+namespace dev {
+
+// Carry fix-up: entry (b, a, row) finishes the segment that tile a starts
+// (its last open partial) and tile b closes (its first partial; b = ntiles
+// is the end of the tensor), with tiles a+1 .. b-1 lying wholly inside it.
+__global__ __launch_bounds__(256) void fixup_kernel(const int32_t *__restrict__ fix,
+                                                    const float *__restrict__ ca,
+                                                    const float *__restrict__ cb, int64_t ntiles,
+                                                    int R, float *__restrict__ out)
+{
+    __shared__ float red[256];
+    const int64_t e = blockIdx.x;
+    const int tb = fix[3 * e], ta = fix[3 * e + 1], row = fix[3 * e + 2];
+    const int tid = threadIdx.x;
+    const int slots = 256 / R;
+    const int slot = tid / R, c = tid - (tid / R) * R;
+    float s = 0.f;
+    if (slot < slots)
+        for (int64_t t = (int64_t)ta + 1 + slot; t < tb; t += slots) s += ca[t * R + c];
+    red[tid] = s;
+    __syncthreads();
+    if (tid < R) {
+        float v = cb[(int64_t)ta * R + tid];
+        for (int k = 0; k < slots; ++k) v += red[k * R + tid];
+        if (tb < ntiles) v += ca[(int64_t)tb * R + tid];
+        out[(int64_t)row * R + tid] = v;
+    }
+}
+
+// Rows of an MTTKRP result that no nonzero touches are zero.
+__global__ __launch_bounds__(256) void zero_rows_kernel(const int32_t *__restrict__ rows, int64_t nrows,
+                                                        int R, float *__restrict__ out)
+{
+    const int64_t n = nrows * R;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t r = i / R;
+        out[(int64_t)rows[r] * R + (i - r * R)] = 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void permute_kernel(const int32_t *__restrict__ perm,
+                                                      const float *__restrict__ g, int64_t n,
+                                                      float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        out[i] = g[perm[i]];
+}
+
+// One workgroup: fixed-order strided sums, then a tree; bitwise repeatable.
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const double *__restrict__ p, int64_t n,
+                                                              double scale, double *__restrict__ out)
+{
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = tid; i < n; i += 256) s += p[i];
+    sh[tid] = s;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (tid < o) sh[tid] += sh[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = sh[0] * scale;
+}
+
+struct ModelArgs {
+    const int32_t *idx[kMaxOrder];
+    const void *fac[kMaxOrder];
+    float *xhat;
+    int64_t nnz;
+    int order;
+    int R;
+};
+
+// xhat[e] = sum_r prod_m A_m[i_m(e), r]: a lane group of LPN lanes per
+// nonzero, VW columns per lane, rank tiles looped inside (R <= 256).
+template <typename FT, int VW, int LPN>
+__global__ __launch_bounds__(256) void model_kernel(ModelArgs A)
+{
+    constexpr int Q = 64 / LPN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int q = lane / LPN, j = lane % LPN;
+    const int64_t stride = (int64_t)gridDim.x * 4 * Q;
+    for (int64_t e = ((int64_t)blockIdx.x * 4 + w) * Q + q; e < A.nnz; e += stride) {
+        int ix[kMaxOrder];
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) ix[m] = m < A.order ? __builtin_nontemporal_load(A.idx[m] + e) : 0;
+        float s = 0.f;
+        for (int c0 = 0; c0 < A.R; c0 += LPN * VW) {
+            const int col = c0 + j * VW;
+            if (col < A.R) {
+                Raw<FT, VW> raw[kMaxOrder];
+#pragma unroll
+                for (int m = 0; m < kMaxOrder; ++m)
+                    if (m < A.order) load_raw<FT, VW>(reinterpret_cast<const FT *>(A.fac[m]) + (int64_t)ix[m] * A.R + col, raw[m]);
+                float p[VW];
+                to_float<FT, VW>(raw[0], p);
+#pragma unroll
+                for (int m = 1; m < kMaxOrder; ++m) {
+                    if (m < A.order) {
+                        float x[VW];
+                        to_float<FT, VW>(raw[m], x);
+#pragma unroll
+                        for (int k = 0; k < VW; ++k) p[k] *= x[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < VW; ++k) s += p[k];
+            }
+        }
+        s = group_sum<LPN>(s);
+        if (j == 0) A.xhat[e] = s;
+    }
+}
+
+}  // namespace dev
+
+static int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static int grid_for(int64_t work, int64_t per_block, int cap = 65535 * 8)
+{
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
+{
+    const Built &b = *p.b;
+    const int R = p.R;
+    if (b.nnz > 0) {
+        SegLaunch L{};
+        dev::SegArgs &a = L.args;
+        const int np = (int)b.pmodes.size();
+        for (int q = 0; q < np; ++q) {
+            a.pidx[q] = b.d_pidx[q];
+            a.fac[q] = p.fac[q];
+        }
+        a.vals = p.vals;
+        a.bf = b.d_bf;
+        a.tile_seg0 = b.d_tile_seg0;
+        a.seg_row = b.op == FCOO_OP_MTTKRP ? b.d_seg_row : nullptr;
+        a.out = p.out;
+        a.carry_a = p.carry;
+        a.carry_b = p.carry + b.ntiles * (int64_t)R;
+        a.own = p.own;
+        a.partial = p.partial;
+        a.nnz = b.nnz;
+        a.ntiles = b.ntiles;
+        a.R = R;
+        a.np = np;
+        a.tile_nnz = b.tile_nnz;
+        a.inv_nnz = p.inv_nnz;
+        const int V = p.dtype == FCOO_F32 ? 4 : 8;
+        L.vec = (R % V) == 0;
+        const int VW = L.vec ? V : 1;
+        int lpn = next_pow2((R + VW - 1) / VW);
+        if (L.vec && lpn > 16) lpn = 16;
+        if (!L.vec) lpn = 64;
+        L.lpn = lpn;
+        const int rt = lpn * VW;
+        const int nrt = (R + rt - 1) / rt;
+        if (resid && nrt > 1)
+            return fail(FCOO_EUNSUPPORTED, "fused residual needs R <= %d for this dtype (R = %d)", rt, R);
+        L.npt = np <= 3 ? np : 0;
+        L.grid = dim3((unsigned)b.ntiles, (unsigned)nrt, 1);
+        hipError_t e;
+        if (p.ev_before) FCOO_HIP(hipEventRecord(p.ev_before, s));
+        if (p.dtype == FCOO_F32) e = resid ? seg_launch_f32_resid(L, s) : seg_launch_f32(L, s);
+        else e = resid ? seg_launch_bf16_resid(L, s) : seg_launch_bf16(L, s);
+        if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+        if (p.ev_after) FCOO_HIP(hipEventRecord(p.ev_after, s));
+        const int64_t nfix = b.nfix();
+        if (nfix > 0) {
+            hipLaunchKernelGGL(dev::fixup_kernel, dim3((unsigned)nfix), dim3(256), 0, s, b.d_fix,
+                               a.carry_a, a.carry_b, b.ntiles, R, p.out);
+            FCOO_HIP(hipGetLastError());
+        }
+    }
+    const int64_t nempty = (int64_t)b.empty_rows.size();
+    if (nempty > 0) {
+        hipLaunchKernelGGL(dev::zero_rows_kernel, dim3(grid_for(nempty * R, 256)), dim3(256), 0, s,
+                           b.d_empty, nempty, R, p.out);
+        FCOO_HIP(hipGetLastError());
+    }
+    return FCOO_OK;
+}
+
+int launch_permute_values(const Built &b, const float *g, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::permute_kernel, dim3(grid_for(b.nnz, 256 * 8)), dim3(256), 0, s, b.d_perm, g,
+                       b.nnz, out);
+    FCOO_HIP(hipGetLastError());
+    return FCOO_OK;
+}
+
+int launch_reduce_partials(const double *partial, int64_t n, double scale, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(dev::reduce_partials_kernel, dim3(1), dim3(256), 0, s, partial, n, scale, out);
+    FCOO_HIP(hipGetLastError());
+    return FCOO_OK;
+}
+
+template <typename FT>
+static hipError_t model_go(const dev::ModelArgs &a, bool vec, int lpn, hipStream_t s)
+{
+    constexpr int V = dev::Elem<FT>::VEC;
+    auto grid = [&](int L) { return dim3(grid_for(a.nnz, 4 * (64 / L) * 4, 65535 * 4)); };
+    if (!vec) {
+        hipLaunchKernelGGL((dev::model_kernel<FT, 1, 64>), grid(64), dim3(256), 0, s, a);
+    } else {
+        switch (lpn) {
+            case 1: hipLaunchKernelGGL((dev::model_kernel<FT, V, 1>), grid(1), dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL((dev::model_kernel<FT, V, 2>), grid(2), dim3(256), 0, s, a); break;
+            case 4: hipLaunchKernelGGL((dev::model_kernel<FT, V, 4>), grid(4), dim3(256), 0, s, a); break;
+            case 8: hipLaunchKernelGGL((dev::model_kernel<FT, V, 8>), grid(8), dim3(256), 0, s, a); break;
+            default: hipLaunchKernelGGL((dev::model_kernel<FT, V, 16>), grid(16), dim3(256), 0, s, a); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+int launch_model(const fcoo_tensor *t, const void *const *factors, int dtype, int R, float *xhat,
+                 hipStream_t s)
+{
+    if (t->nnz == 0) return FCOO_OK;
+    dev::ModelArgs a{};
+    for (int m = 0; m < t->order; ++m) {
+        a.idx[m] = t->d_coo[m];
+        a.fac[m] = factors[m];
+    }
+    a.xhat = xhat;
+    a.nnz = t->nnz;
+    a.order = t->order;
+    a.R = R;
+    const int V = dtype == FCOO_F32 ? 4 : 8;
+    const bool vec = R % V == 0;
+    int lpn = next_pow2((R + V - 1) / V);
+    if (lpn > 16) lpn = 16;
+    hipError_t e = dtype == FCOO_F32 ? model_go<float>(a, vec, lpn, s) : model_go<dev::bf16raw>(a, vec, lpn, s);
+    if (e != hipSuccess) return hip_fail(e, "model kernel launch");
+    return FCOO_OK;
+}
+
+}  // namespace fcoo

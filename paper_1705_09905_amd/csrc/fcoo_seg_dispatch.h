@@ -1,0 +1,56 @@
+// Picks the tile-kernel instantiation for a (storage type, lane layout,
+// number of product modes) and launches it.  Included by the four
+// instantiation units (float32 / bfloat16, plain / fused residual), which
+// are compiled separately to keep build times short.
+#pragma once
+
+#include "fcoo_segscan.h"
+
+namespace fcoo {
+
+struct SegLaunch {
+    dev::SegArgs args;
+    bool vec;        // 16-byte row chunks per lane (R a multiple of the vector width)
+    int lpn;         // lanes per nonzero: 1, 2, 4, 8, 16 (vector) or 64 (scalar)
+    int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
+    dim3 grid;
+};
+
+template <typename FT, int VW, int LPN, int NP, bool RESID>
+static hipError_t seg_go(const SegLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, RESID>), L.grid, dim3(256), 0, s, L.args);
+    return hipGetLastError();
+}
+
+template <typename FT, int VW, int LPN, bool RESID>
+static hipError_t seg_np(const SegLaunch &L, hipStream_t s)
+{
+    switch (L.npt) {
+        case 1: return seg_go<FT, VW, LPN, 1, RESID>(L, s);
+        case 2: return seg_go<FT, VW, LPN, 2, RESID>(L, s);
+        case 3: return seg_go<FT, VW, LPN, 3, RESID>(L, s);
+        default: return seg_go<FT, VW, LPN, 0, RESID>(L, s);
+    }
+}
+
+template <typename FT, bool RESID>
+static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
+{
+    constexpr int V = dev::Elem<FT>::VEC;
+    if (!L.vec) return seg_go<FT, 1, 64, 0, RESID>(L, s);
+    switch (L.lpn) {
+        case 1: return seg_np<FT, V, 1, RESID>(L, s);
+        case 2: return seg_np<FT, V, 2, RESID>(L, s);
+        case 4: return seg_np<FT, V, 4, RESID>(L, s);
+        case 8: return seg_np<FT, V, 8, RESID>(L, s);
+        default: return seg_np<FT, V, 16, RESID>(L, s);
+    }
+}
+
+hipError_t seg_launch_f32(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_bf16(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_f32_resid(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_bf16_resid(const SegLaunch &L, hipStream_t s);
+
+}  // namespace fcoo

@@ -1,0 +1,142 @@
+"""Host logic of the library, no GPU needed: the C ABI loads and exports every
+symbol include/fcoo.h declares; the host F-COO builder is bit-exact against
+the oracle's reference encoder; bad arguments return the documented codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ref
+
+from conftest import ROOT
+
+from paper_1705_09905_amd import FcooError, Tensor, _lib
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "fcoo.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcoo_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(_lib.lib, n), n
+        assert getattr(_lib.lib, n) is not None
+    assert _lib.lib.fcoo_version() == 100
+
+
+def _build_both(t, mode, op, L, T):
+    h = Tensor(t.idx, t.vals, t.dims)
+    h.build(mode, op, threadlen=L, tile_nnz=T, host_only=True)
+    got = h.export(mode, op)
+    exp = ref.fcoo_encode(t.dims, t.idx, t.vals.astype(np.float32), mode,
+                          ref.OP_MTTKRP if op == "mttkrp" else ref.OP_TTM, L, T)
+    return h, got, exp
+
+
+def _assert_same(got, exp, op):
+    assert got["nseg"] == exp["nseg"]
+    for a, b in zip(got["pidx"], exp["pidx"]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(got["val"], exp["val"])
+    np.testing.assert_array_equal(got["bf"], exp["bf"])
+    np.testing.assert_array_equal(got["sf"], exp["sf"])
+    np.testing.assert_array_equal(got["tile_seg0"], exp["tile_seg0"])
+    np.testing.assert_array_equal(got["perm"], exp["perm"])
+    if op == "mttkrp":
+        np.testing.assert_array_equal(got["seg_row"], exp["seg_row"])
+    else:
+        np.testing.assert_array_equal(got["fibres"], exp["fibres"])
+
+
+@pytest.mark.parametrize("dims,Z,seed", [([7, 5, 6], 150, 1), ([3, 4, 5, 2], 100, 2), ([50, 3], 120, 3),
+                                          ([9, 8, 7, 3, 2], 333, 5), ([1, 6, 5], 25, 6),
+                                          ([40, 30, 20], 5000, 7), ([6, 5, 4, 3, 2, 2, 2, 2], 700, 8)])
+@pytest.mark.parametrize("op", ["mttkrp", "ttm"])
+@pytest.mark.parametrize("L,T", [(8, 256), (16, 512), (64, 256)])
+def test_builder_bit_exact_vs_oracle_encoder(dims, Z, seed, op, L, T):
+    t = synth.random_small(dims, Z, seed=seed)
+    for mode in range(len(dims)):
+        _, got, exp = _build_both(t, mode, op, L, T)
+        _assert_same(got, exp, op)
+
+
+def test_builder_duplicates_and_golden():
+    t = synth.random_small([6, 5, 4], 400, seed=9, duplicates=True)
+    for op in ("mttkrp", "ttm"):
+        for mode in range(3):
+            _, got, exp = _build_both(t, mode, op, 8, 256)
+            _assert_same(got, exp, op)
+
+
+def test_builder_large_keys_fall_back_to_comparison_sort():
+    # 8 modes of 2^9 = 72 key bits > 64: the comparison sort path
+    g = np.random.default_rng(3)
+    dims = [512] * 8
+    Z = 3000
+    idx = [g.integers(0, 512, Z).astype(np.int32) for _ in range(8)]
+    idx[1][:100] = idx[1][100:200]  # some repeated prefixes
+    vals = g.random(Z)
+    t = synth.SparseTensor(dims=dims, idx=idx, vals=vals)
+    for op in ("mttkrp", "ttm"):
+        _, got, exp = _build_both(t, 3, op, 16, 512)
+        _assert_same(got, exp, op)
+
+
+def test_builder_radix_path_large():
+    t = synth.zipf_tensor([3000, 2000, 1000], 200_000, cfg=77)
+    for op in ("mttkrp", "ttm"):
+        _, got, exp = _build_both(t, 1, op, 16, 4096)
+        _assert_same(got, exp, op)
+
+
+def test_info_sizes_match_table2():
+    t = synth.random_small([64, 64, 64], 8 * 32 * 16, seed=4)
+    h = Tensor(t.idx, t.vals, t.dims)
+    for op in ("mttkrp", "ttm"):
+        h.build(0, op, threadlen=16, tile_nnz=256, host_only=True)
+        inf = h.info(0, op)
+        assert inf["bytes_format"] == ref.table2_bytes(t.nnz, 0 if op == "mttkrp" else 1, 16)
+        assert inf["on_device"] == 0
+
+
+def test_empty_tensor_builds():
+    h = Tensor([np.zeros(0, np.int32)] * 3, np.zeros(0), [4, 5, 6])
+    h.build(1, "mttkrp", host_only=True)
+    inf = h.info(1)
+    assert inf["nnz"] == 0 and inf["nseg"] == 0 and inf["ntiles"] == 0 and inf["nempty"] == 5
+    e = h.export(1)
+    assert e["bf"].size == 0 and e["sf"].size == 0
+
+
+def _code(fn):
+    with pytest.raises(FcooError) as ei:
+        fn()
+    return ei.value.code
+
+
+def test_error_codes():
+    assert _code(lambda: Tensor([np.array([0, 5], np.int32), np.array([0, 0], np.int32)],
+                                [1.0, 2.0], [5, 3])) == _lib.FCOO_ERANGE
+    assert _code(lambda: Tensor([np.array([-1], np.int32), np.array([0], np.int32)], [1.0],
+                                [5, 3])) == _lib.FCOO_ERANGE
+    assert _code(lambda: Tensor([np.array([0], np.int32)], [1.0], [5])) == _lib.FCOO_EUNSUPPORTED
+    h = Tensor([np.array([0, 1], np.int32), np.array([2, 0], np.int32)], [1.0, 2.0], [3, 3])
+    assert _code(lambda: h.info(0)) == _lib.FCOO_ENOTBUILT
+    assert _code(lambda: h.build(2, "mttkrp", host_only=True)) == _lib.FCOO_EINVAL
+    assert _code(lambda: h.build(0, "mttkrp", threadlen=12, host_only=True)) == _lib.FCOO_EINVAL
+    assert _code(lambda: h.build(0, "mttkrp", tile_nnz=100, host_only=True)) == _lib.FCOO_EINVAL
+    h.build(0, "mttkrp", host_only=True)
+    # a host-only build is not on the device: device operations refuse it
+    rc = _lib.fcoo_spmttkrp(h.handle, 0, _lib.ptr_array([1, 1]), 0, 4, C.c_void_p(1), None)
+    assert rc == _lib.FCOO_ENOTBUILT
+    rc = _lib.fcoo_create(2, None, 0, None, None, C.byref(C.c_void_p()))
+    assert rc == _lib.FCOO_EINVAL
+    assert b"dims" in _lib.fcoo_last_error()
