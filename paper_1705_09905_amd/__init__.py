@@ -10,5 +10,6 @@ this package marshals arguments and uses torch for device memory and streams.
 from . import _lib  # noqa: F401  (fails loudly if libfcoo.so is missing)
 from ._lib import FcooError  # noqa: F401
 from .tensor import Tensor  # noqa: F401
+from .cp import CPAtNonzeros, CPMSELoss, cp_als  # noqa: F401
 
-__all__ = ["Tensor", "FcooError"]
+__all__ = ["Tensor", "FcooError", "cp_als", "CPAtNonzeros", "CPMSELoss"]

@@ -164,6 +164,7 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.R = R;
         a.np = np;
         a.tile_nnz = b.tile_nnz;
+        a.nseg = (int)b.nseg;
         a.inv_nnz = p.inv_nnz;
         const int V = p.dtype == FCOO_F32 ? 4 : 8;
         L.vec = (R % V) == 0;
@@ -177,6 +178,7 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         if (resid && nrt > 1)
             return fail(FCOO_EUNSUPPORTED, "fused residual needs R <= %d for this dtype (R = %d)", rt, R);
         L.npt = np <= 3 ? np : 0;
+        L.rowmap = b.op == FCOO_OP_MTTKRP;
         L.grid = dim3((unsigned)b.ntiles, (unsigned)nrt, 1);
         hipError_t e;
         if (p.ev_before) FCOO_HIP(hipEventRecord(p.ev_before, s));

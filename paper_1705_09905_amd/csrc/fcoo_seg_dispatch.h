@@ -13,24 +13,30 @@ struct SegLaunch {
     bool vec;        // 16-byte row chunks per lane (R a multiple of the vector width)
     int lpn;         // lanes per nonzero: 1, 2, 4, 8, 16 (vector) or 64 (scalar)
     int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
+    bool rowmap;     // output row = seg_row[segment] (SpMTTKRP) or the segment ordinal (SpTTM)
     dim3 grid;
 };
 
-template <typename FT, int VW, int LPN, int NP, bool RESID>
+template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP>
 static hipError_t seg_go(const SegLaunch &L, hipStream_t s)
 {
-    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, RESID>), L.grid, dim3(256), 0, s, L.args);
+    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, RESID, ROWMAP>), L.grid, dim3(256), 0, s,
+                       L.args);
     return hipGetLastError();
 }
 
+// SpTTM has one product mode and identity row map; SpMTTKRP maps rows.
 template <typename FT, int VW, int LPN, bool RESID>
 static hipError_t seg_np(const SegLaunch &L, hipStream_t s)
 {
+    if constexpr (!RESID) {
+        if (!L.rowmap) return seg_go<FT, VW, LPN, 1, false, false>(L, s);
+    }
     switch (L.npt) {
-        case 1: return seg_go<FT, VW, LPN, 1, RESID>(L, s);
-        case 2: return seg_go<FT, VW, LPN, 2, RESID>(L, s);
-        case 3: return seg_go<FT, VW, LPN, 3, RESID>(L, s);
-        default: return seg_go<FT, VW, LPN, 0, RESID>(L, s);
+        case 1: return seg_go<FT, VW, LPN, 1, RESID, true>(L, s);
+        case 2: return seg_go<FT, VW, LPN, 2, RESID, true>(L, s);
+        case 3: return seg_go<FT, VW, LPN, 3, RESID, true>(L, s);
+        default: return seg_go<FT, VW, LPN, 0, RESID, true>(L, s);
     }
 }
 
@@ -38,7 +44,12 @@ template <typename FT, bool RESID>
 static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
 {
     constexpr int V = dev::Elem<FT>::VEC;
-    if (!L.vec) return seg_go<FT, 1, 64, 0, RESID>(L, s);
+    if (!L.vec) {
+        if constexpr (!RESID) {
+            if (!L.rowmap) return seg_go<FT, 1, 64, 0, false, false>(L, s);
+        }
+        return seg_go<FT, 1, 64, 0, RESID, true>(L, s);
+    }
     switch (L.lpn) {
         case 1: return seg_np<FT, V, 1, RESID>(L, s);
         case 2: return seg_np<FT, V, 2, RESID>(L, s);

@@ -57,6 +57,7 @@ struct SegArgs {
     int R;
     int np;                          // number of product modes (runtime, for NP == 0)
     int tile_nnz;
+    int nseg;                        // number of segments
     float inv_nnz;                   // RESID: 1 / Z
 };
 
@@ -104,19 +105,82 @@ __device__ __forceinline__ void wave_segscan(int &f, float (&a)[VW], float (&b)[
     }
 }
 
-template <typename FT, int VW, int LPN, int NP, bool RESID>
+constexpr int pow2_floor(int x)
+{
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+// The stream of one chunk as held by one lane: U entries per array (entry
+// u of lane j is step u * LPN + j of the chunk), the three bf words that
+// cover nonzeros [base - 1, base + 63] (decoded only when the chunk is
+// used, so that loading the next chunk never waits), and the chunk length.
+template <int U, int NPM>
+struct Chunk {
+    int idx[U][NPM];
+    float v[U];
+    uint32_t w0, w1, w2;
+    int sh;                      // bit of nonzero base - 1 in w0; -1 when base == 0
+    int n;
+};
+
+template <int LPN, int CL, int U, int NPM>
+__device__ __forceinline__ void load_chunk(const SegArgs &A, int np, int j, int64_t base, int64_t re,
+                                           Chunk<U, NPM> &c)
+{
+    const int64_t rem = re - base;
+    c.n = rem < CL ? (int)rem : CL;
+    const int64_t p1 = base - 1;
+    const int64_t wi = p1 < 0 ? 0 : (p1 >> 5);
+    c.sh = p1 < 0 ? -1 : (int)(p1 & 31);
+    c.w0 = A.bf[wi];
+    c.w1 = A.bf[wi + 1];
+    c.w2 = A.bf[wi + 2];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int el = u * LPN + j;
+        const bool ev = el < c.n;
+        const int64_t e = base + el;
+#pragma unroll
+        for (int qq = 0; qq < NPM; ++qq)
+            c.idx[u][qq] = (ev && qq < np) ? __builtin_nontemporal_load(A.pidx[qq] + e) : 0;
+        c.v[u] = ev ? __builtin_nontemporal_load(A.vals + e) : 0.f;
+    }
+}
+
+// Segment heads of the chunk's n steps (bit s: step s starts a segment).
+template <int U, int NPM>
+__device__ __forceinline__ uint64_t chunk_heads(const Chunk<U, NPM> &c)
+{
+    const uint64_t lo = (uint64_t)c.w0 | ((uint64_t)c.w1 << 32);
+    const int sh = c.sh < 0 ? 0 : c.sh;
+    const uint64_t x = sh ? ((lo >> sh) | ((uint64_t)c.w2 << (64 - sh))) : lo;  // from nonzero base - 1
+    const uint64_t top = (c.w2 >> sh) & 1u;                                       // nonzero base + 63
+    const uint64_t cur = c.sh < 0 ? lo : ((x >> 1) | (top << 63));
+    const uint64_t prev = c.sh < 0 ? 0ull : (x & 1ull);
+    const uint64_t hm = cur ^ ((cur << 1) | prev);
+    return c.n >= 64 ? hm : (hm & ((1ull << c.n) - 1ull));
+}
+
+template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP>
 __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
     constexpr int NPM = NP > 0 ? NP : kMaxNP;         // product modes held per step
-    constexpr int CH = NP > 0 ? (LPN < 8 ? LPN : 8) : (LPN < 2 ? LPN : 2);  // steps per gather batch
+    constexpr int RAWREGS = (int)(sizeof(Raw<FT, VW>) / 4);
+    // gathers in flight per lane: about 64 registers of raw rows
+    constexpr int CH0 = NP > 0 ? pow2_floor(64 / (NPM * RAWREGS)) : 2;
+    constexpr int CL = CH0 > LPN ? CH0 : LPN;         // steps per chunk (stream granule)
+    constexpr int CH = CH0 < CL ? CH0 : CL;           // steps per gather batch
+    constexpr int U = CL / LPN;                       // stream entries per lane per chunk
     constexpr int RT = LPN * VW;                      // columns of this rank tile
 
-    __shared__ int s_cnt[4];
     __shared__ int s_f[4];
     __shared__ float s_a[4][RT];
     __shared__ float s_b[4][RT];
     __shared__ double s_loss[4];
+    __shared__ int s_hw[4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -125,14 +189,37 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     const int T = A.tile_nnz;
     const int S = T / (4 * Q);                        // run length of one lane group
     const int64_t t0 = tile * (int64_t)T;
-    const int64_t rs = t0 + (int64_t)(w * Q + q) * S;
+    const int64_t wstart = t0 + (int64_t)w * Q * S;
+    const int64_t rs = wstart + (int64_t)q * S;
     const int64_t re = rs + S < A.nnz ? rs + S : A.nnz;
     const int col = (int)blockIdx.y * RT + j * VW;
     const bool cval = col < A.R;
+    const int colc = cval ? col : 0;                  // lanes past R read column 0, never store
     const int R = A.R;
     const int np = NP > 0 ? NP : A.np;
+    const uint64_t R4 = (uint64_t)R * sizeof(FT);
+    const char *fb[NPM];
+#pragma unroll
+    for (int qq = 0; qq < NPM; ++qq)
+        fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)colc * sizeof(FT);
 
-    // ---- 1. heads before each run: tile prefix from tile_seg0, then counts
+    // first chunk of the stream and the tile's segment ordinal: issued first
+    Chunk<U, NPM> cur;
+    if (rs < re) load_chunk<LPN, CL, U, NPM>(A, np, j, rs, re, cur);
+    const int ts0 = A.tile_seg0[tile];
+    const int h0 = (int)head_at(A.bf, t0);
+
+    // ---- 1. heads before each run.  Heads in [t0, wave start): counted by
+    //         the whole wave; heads of the earlier runs of this wave: a scan
+    //         across lane groups.  No barrier.
+    int wc = 0;
+    const int64_t wend = wstart < A.nnz ? wstart : A.nnz;   // no bits exist at or past Z
+    for (int64_t p = t0 + 64 * (int64_t)lane; p < wend; p += 64 * 64) {
+        const int n = (int)(wend - p < 64 ? wend - p : 64);
+        wc += __popcll(head_window(A.bf, p, n));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) wc += __shfl_xor(wc, o, 64);
     int cnt = 0;
     for (int64_t base = rs; base < re; base += 64) {
         const int n = (int)(re - base < 64 ? re - base : 64);
@@ -144,106 +231,161 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         const int u = __shfl_up(inc, d * LPN, 64);
         if (q >= d) inc += u;
     }
-    if (lane == 63) s_cnt[w] = inc;
-    __syncthreads();
-    int wave_before = 0;
-    for (int i = 0; i < w; ++i) wave_before += s_cnt[i];
     // heads strictly before the tile: ordinal of its first nonzero + 1, less
     // one if that nonzero is itself a head
-    const int H_tile = A.tile_seg0[tile] + 1 - (int)head_at(A.bf, t0);
-    const int H_wave = H_tile + wave_before;
+    const int H_tile = ts0 + 1 - h0;
+    const int H_wave = H_tile + wc;
     const int H_run = H_wave + inc - cnt;
 
-    // ---- 2. walk the run
+    // ---- 2. walk the run, one chunk at a time: gather this chunk's rows,
+    //         then put the next chunk's stream in flight, then reduce
     float acc[VW], pre[VW];
     zero(acc);
     zero(pre);
     int have = 0;
     int g = H_run - 1;                                // segment open before the run
+    int currow = 0;                                   // ROWMAP: output row of segment g
     float own[VW];
     float lsum = 0.f;
     if constexpr (RESID) {
         zero(own);
-        if (g >= 0 && rs < re && cval)
-            load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)A.seg_row[g] * R + col, own);
+        if (g >= 0 && rs < re) {
+            currow = A.seg_row[g];
+            load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)currow * R + colc, own);
+        }
     }
 
-    for (int64_t base = rs; base < re; base += 64) {
-        const int n = (int)(re - base < 64 ? re - base : 64);
-        const uint64_t hm = head_window(A.bf, base, n);
-        for (int c = 0; c < n; c += LPN) {
-            const int el = c + j;
-            const bool ev = el < n;
-            const int64_t e = base + el;
-            int my_idx[NPM];
+    // one step of the general path (a head may occur, the chunk may be short)
+    auto step = [&](const float (&h)[VW], float v, uint64_t hm, int st, int n) {
+        if ((hm >> st) & 1ull) {
+            if (have && cval) {
+                const int64_t row = ROWMAP ? (int64_t)currow : (int64_t)g;
+                store_row<VW>(A.out + row * R + col, acc);
+            }
+            if (!have) {
 #pragma unroll
-            for (int qq = 0; qq < NPM; ++qq)
-                my_idx[qq] = (ev && qq < np) ? __builtin_nontemporal_load(A.pidx[qq] + e) : 0;
-            const float my_v = ev ? __builtin_nontemporal_load(A.vals + e) : 0.f;
+                for (int k = 0; k < VW; ++k) pre[k] = acc[k];
+            }
+            have = 1;
+            zero(acc);
+            ++g;
+            if constexpr (ROWMAP) currow = A.seg_row[g];
+            if constexpr (RESID)
+                load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)currow * R + colc, own);
+        }
+        if (st < n) {
+            if constexpr (RESID) {
+                float d = 0.f;
+#pragma unroll
+                for (int k = 0; k < VW; ++k) d += own[k] * h[k];
+                d = group_sum<LPN>(d);
+                const float r = d - v;
+                const float sc = r * A.inv_nnz;
+#pragma unroll
+                for (int k = 0; k < VW; ++k) acc[k] += sc * h[k];
+                if (j == 0) lsum += r * r;
+            } else {
+#pragma unroll
+                for (int k = 0; k < VW; ++k) acc[k] += v * h[k];
+            }
+        }
+    };
 
-            static_for<LPN / CH>([&](auto c2c) {
-                constexpr int C2 = decltype(c2c)::value * CH;
-                Raw<FT, VW> rows[CH][NPM];
-                static_for<CH>([&](auto jjc) {
-                    constexpr int JJ = decltype(jjc)::value;
+    for (int64_t base = rs; base < re; base += CL) {
+        Chunk<U, NPM> nxt;
+        const bool more = base + CL < re;
+        if constexpr (CH == CL && NP > 0) {
+            // all rows of the chunk in flight at once
+            Raw<FT, VW> rows[CL][NPM];
+            int gi[CL][NPM];
+            static_for<CL>([&](auto sc) {
+                constexpr int ST = decltype(sc)::value;
 #pragma unroll
-                    for (int qq = 0; qq < NPM; ++qq) {
-                        const int idx = bcast_imm<LPN, C2 + JJ>(my_idx[qq]);
-                        if (cval && qq < np)
-                            load_raw<FT, VW>(reinterpret_cast<const FT *>(A.fac[qq]) + (int64_t)idx * R + col,
-                                             rows[JJ][qq]);
-                        else
-                            set_one<FT, VW>(rows[JJ][qq]);
-                    }
-                });
-                static_for<CH>([&](auto jjc) {
-                    constexpr int JJ = decltype(jjc)::value;
-                    const int st = c + C2 + JJ;
-                    const float v = bcast_imm_f<LPN, C2 + JJ>(my_v);
+                for (int qq = 0; qq < NPM; ++qq) gi[ST][qq] = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
+            });
+            static_for<CL>([&](auto sc) {
+                constexpr int ST = decltype(sc)::value;
+#pragma unroll
+                for (int qq = 0; qq < NPM; ++qq)
+                    load_raw<FT, VW>(reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)gi[ST][qq] * R4),
+                                     rows[ST][qq]);
+            });
+            if (more) load_chunk<LPN, CL, U, NPM>(A, np, j, base + CL, re, nxt);
+            float vv[CL];
+            static_for<CL>([&](auto sc) {
+                constexpr int ST = decltype(sc)::value;
+                vv[ST] = bcast_imm_f<LPN, ST % LPN>(cur.v[ST / LPN]);
+            });
+            const uint64_t hm = chunk_heads(cur);
+            const int n = cur.n;
+            const bool easy = !RESID && __ballot(hm != 0ull || n < CL) == 0ull;
+            if (easy) {
+                static_for<CL>([&](auto sc) {
+                    constexpr int ST = decltype(sc)::value;
                     float h[VW];
-                    to_float<FT, VW>(rows[JJ][0], h);
+                    to_float<FT, VW>(rows[ST][0], h);
 #pragma unroll
                     for (int qq = 1; qq < NPM; ++qq) {
                         float x[VW];
-                        to_float<FT, VW>(rows[JJ][qq], x);
+                        to_float<FT, VW>(rows[ST][qq], x);
 #pragma unroll
                         for (int k = 0; k < VW; ++k) h[k] *= x[k];
                     }
-                    if ((hm >> st) & 1ull) {
-                        if (!have) {
 #pragma unroll
-                            for (int k = 0; k < VW; ++k) pre[k] = acc[k];
-                            have = 1;
-                        } else if (cval) {
-                            const int64_t row = A.seg_row ? (int64_t)A.seg_row[g] : (int64_t)g;
-                            store_row<VW>(A.out + row * R + col, acc);
-                        }
-                        zero(acc);
-                        ++g;
-                        if constexpr (RESID) {
-                            if (cval)
-                                load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)A.seg_row[g] * R + col, own);
-                        }
+                    for (int k = 0; k < VW; ++k) acc[k] += vv[ST] * h[k];
+                });
+            } else {
+                static_for<CL>([&](auto sc) {
+                    constexpr int ST = decltype(sc)::value;
+                    float h[VW];
+                    to_float<FT, VW>(rows[ST][0], h);
+#pragma unroll
+                    for (int qq = 1; qq < NPM; ++qq) {
+                        float x[VW];
+                        to_float<FT, VW>(rows[ST][qq], x);
+#pragma unroll
+                        for (int k = 0; k < VW; ++k) h[k] *= x[k];
                     }
-                    if (st < n) {
-                        if constexpr (RESID) {
-                            float d = 0.f;
+                    step(h, vv[ST], hm, ST, n);
+                });
+            }
+        } else {
+            // generic path: gathers in batches of CH steps, runtime mode count
+            if (more) load_chunk<LPN, CL, U, NPM>(A, np, j, base + CL, re, nxt);
+            const uint64_t hm = chunk_heads(cur);
+            const int n = cur.n;
+            static_for<CL / CH>([&](auto sbc) {
+                constexpr int S0 = decltype(sbc)::value * CH;
+                Raw<FT, VW> rows[CH][NPM];
+                static_for<CH>([&](auto jjc) {
+                    constexpr int ST = S0 + decltype(jjc)::value;
 #pragma unroll
-                            for (int k = 0; k < VW; ++k) d += own[k] * h[k];
-                            d = group_sum<LPN>(d);
-                            const float r = d - v;
-                            const float sc = r * A.inv_nnz;
-#pragma unroll
-                            for (int k = 0; k < VW; ++k) acc[k] += sc * h[k];
-                            if (j == 0) lsum += r * r;
-                        } else {
-#pragma unroll
-                            for (int k = 0; k < VW; ++k) acc[k] += v * h[k];
-                        }
+                    for (int qq = 0; qq < NPM; ++qq) {
+                        const int idx = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
+                        if (qq < np)
+                            load_raw<FT, VW>(reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * R4),
+                                             rows[ST - S0][qq]);
+                        else
+                            set_one<FT, VW>(rows[ST - S0][qq]);
                     }
+                });
+                static_for<CH>([&](auto jjc) {
+                    constexpr int ST = S0 + decltype(jjc)::value;
+                    const float v = bcast_imm_f<LPN, ST % LPN>(cur.v[ST / LPN]);
+                    float h[VW];
+                    to_float<FT, VW>(rows[ST - S0][0], h);
+#pragma unroll
+                    for (int qq = 1; qq < NPM; ++qq) {
+                        float x[VW];
+                        to_float<FT, VW>(rows[ST - S0][qq], x);
+#pragma unroll
+                        for (int k = 0; k < VW; ++k) h[k] *= x[k];
+                    }
+                    step(h, v, hm, ST, n);
                 });
             });
         }
+        cur = nxt;
     }
 
     // ---- 3. wave-level segmented scan of the runs' (f, a, b)
@@ -268,7 +410,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 #pragma unroll
             for (int k = 0; k < VW; ++k) v[k] = bp[k] + ao[k];
             const int gc = H_run - 1;
-            const int64_t row = A.seg_row ? (int64_t)A.seg_row[gc] : (int64_t)gc;
+            const int64_t row = ROWMAP ? (int64_t)A.seg_row[gc] : (int64_t)gc;
             store_row<VW>(A.out + row * R + col, v);
         }
     }
@@ -286,8 +428,6 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
         if (lane == 0) s_loss[w] = (double)l;
     }
-    // H_wave of every wave, for the cross-wave closings below
-    __shared__ int s_hw[4];
     if (lane == 0) s_hw[w] = H_wave;
     __syncthreads();
 
@@ -308,7 +448,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 #pragma unroll
             for (int k = 0; k < VW; ++k) v[k] = bx[k] + s_a[w][j * VW + k];
             const int gc = s_hw[w] - 1;
-            const int64_t row = A.seg_row ? (int64_t)A.seg_row[gc] : (int64_t)gc;
+            const int64_t row = ROWMAP ? (int64_t)A.seg_row[gc] : (int64_t)gc;
             store_row<VW>(A.out + row * R + col, v);
         }
     }

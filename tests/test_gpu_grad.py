@@ -1,0 +1,138 @@
+"""GPU parity of gradient-based sparse CP: the CP model at the nonzeros, the
+value-replaced SpMTTKRP adjoint, the fused MSE residual SpMTTKRP with its
+loss, the autograd Functions, and a few Adam steps, against the float64
+oracle (chain-rule gradient, itself pinned by finite differences)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cpu, ref
+
+from conftest import gpu_available
+from gpu_util import TOL_BF16, TOL_F32, bf16, f32, from_dev, rel_fro, tag, to_dev
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _P():
+    import paper_1705_09905_amd as P
+    return P
+
+
+@pytest.mark.parametrize("dims,Z,R", [([60, 50, 40], 20000, 16), ([30, 20, 10, 8], 6000, 8),
+                                       ([200, 150, 100], 10000, 3), ([40, 30], 900, 64)])
+def test_model_at_nnz(dims, Z, R):
+    P = _P()
+    t = synth.random_small(dims, Z, seed=R)
+    F = synth.small_factors(dims, R, seed=R)
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    for dtype in ("f32", "bf16"):
+        Fd = [f32(f) if dtype == "f32" else bf16(f) for f in F]
+        tag("model", dims, R, dtype)
+        xh = from_dev(h.model_at_nnz([to_dev(f, dtype) for f in Fd]))
+        assert rel_fro(xh, ref.cp_model_at(t.idx, Fd)) <= TOL_F32
+
+
+@pytest.mark.parametrize("dims,Z,R", [([60, 50, 40], 20000, 16), ([30, 20, 10, 8], 6000, 8),
+                                       ([1, 300, 200], 30000, 32), ([50, 40, 30], 8000, 64),
+                                       ([40, 30, 20], 5000, 5)])
+def test_resid_spmttkrp_and_loss(dims, Z, R):
+    P = _P()
+    import torch
+    t = synth.random_small(dims, Z, seed=Z)
+    F = synth.small_factors(dims, R, seed=Z)
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    for dtype in ("f32", "bf16"):
+        Fd = [f32(f) if dtype == "f32" else bf16(f) for f in F]
+        exp_loss, exp_g = cpu.mse_grad(dims, t.idx, f32(t.vals), Fd)
+        for m in range(len(dims)):
+            h.build(m)
+            loss = torch.zeros((), dtype=torch.float64, device="cuda")
+            tag("resid", dims, R, dtype, "mode", m)
+            G = from_dev(h.resid_spmttkrp(m, [to_dev(f, dtype) for f in Fd], loss=loss))
+            assert rel_fro(G, exp_g[m]) <= 5 * TOL_F32, rel_fro(G, exp_g[m])
+            assert abs(loss.item() - exp_loss) <= 1e-5 * exp_loss
+
+
+def test_autograd_cp_at_nonzeros_backward_is_adjoint():
+    P = _P()
+    import torch
+    dims = [50, 40, 30]
+    t = synth.random_small(dims, 12000, seed=3)
+    F = synth.small_factors(dims, 8, seed=3)
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    for m in range(3):
+        h.build(m)
+    Fd = [to_dev(f32(f)).requires_grad_() for f in F]
+    tag("autograd CPAtNonzeros")
+    xh = P.CPAtNonzeros.apply(h, *Fd)
+    w = np.random.default_rng(1).standard_normal(t.nnz)
+    (xh * torch.tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+    exp = cpu.model_adjoint(dims, t.idx, f32(w), [f32(f) for f in F])
+    for m in range(3):
+        assert rel_fro(from_dev(Fd[m].grad), exp[m]) <= TOL_F32
+
+
+def test_autograd_mse_loss_vs_oracle_and_finite_differences():
+    P = _P()
+    import torch
+    dims = [20, 15, 10]
+    t = synth.random_small(dims, 1500, seed=4)
+    F = synth.small_factors(dims, 4, seed=4)
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    for m in range(3):
+        h.build(m)
+    Fd = [to_dev(f32(f)).requires_grad_() for f in F]
+    loss = P.CPMSELoss.apply(h, "f32", *Fd)
+    loss.backward()
+    exp_g = ref.mse_grad(dims, t.idx, f32(t.vals), [f32(f) for f in F])
+    assert abs(loss.item() - ref.mse_loss(t.idx, f32(t.vals), [f32(f) for f in F])) < 1e-6 * loss.item()
+    for m in range(3):
+        assert rel_fro(from_dev(Fd[m].grad), exp_g[m]) <= 5 * TOL_F32
+    # central differences of the device loss itself (float32 path, coarse step)
+    with torch.no_grad():
+        for (m, i, r) in [(0, 3, 1), (1, 7, 2), (2, 9, 3)]:
+            e = 1e-2
+            Fp = [f.detach().clone() for f in Fd]
+            Fm = [f.detach().clone() for f in Fd]
+            Fp[m][i, r] += e
+            Fm[m][i, r] -= e
+            fd = (P.CPMSELoss.apply(h, "f32", *Fp).item() - P.CPMSELoss.apply(h, "f32", *Fm).item()) / (2 * e)
+            g = Fd[m].grad[i, r].item()
+            assert abs(fd - g) <= 1e-3 * max(1e-3, abs(g)) + 1e-6
+
+
+def test_gradient_cp_adam_bf16_and_fp32_track_oracle():
+    P = _P()
+    import torch
+    dims = [300, 200, 100]
+    Pl = synth.small_factors(dims, 4, seed=9)
+    t = synth.random_small(dims, 40000, seed=9)
+    vals = ref.cp_model_at(t.idx, Pl) + np.random.default_rng(0).normal(0, 0.1, t.nnz)
+    t = synth.SparseTensor(dims=dims, idx=t.idx, vals=vals)
+    init = [0.5 * a for a in synth.small_factors(dims, 4, seed=10)]
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    for m in range(3):
+        h.build(m)
+    # oracle Adam in float64 on the float32-rounded start
+    po = [f32(a) for a in init]
+    mo = [np.zeros_like(a) for a in po]
+    vo = [np.zeros_like(a) for a in po]
+    steps = 30
+    for s in range(1, steps + 1):
+        g = ref.mse_grad(dims, t.idx, f32(t.vals), po)
+        po, mo, vo = ref.adam_step(po, g, mo, vo, s, lr=1e-2)
+    fit_o = ref.observed_fit(t.idx, f32(t.vals), po)
+    for dtype in ("f32", "bf16"):
+        masters = [to_dev(f32(a)).requires_grad_() for a in init]
+        opt = torch.optim.Adam(masters, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+        tag("adam", dtype)
+        for s in range(steps):
+            opt.zero_grad()
+            loss = P.CPMSELoss.apply(h, dtype, *masters)
+            loss.backward()
+            opt.step()
+        fit = ref.observed_fit(t.idx, f32(t.vals), [from_dev(m) for m in masters])
+        tag("fit", dtype, fit, "oracle", fit_o)
+        assert abs(fit - fit_o) <= 1e-3
