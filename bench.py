@@ -86,7 +86,7 @@ class HipEvents:
         self.events = []
 
 
-def cpu_baseline(t, Rs, sample_nnz, threads):
+def cpu_baseline(t, Rs, sample_nnz, threads, cp=None):
     """The float64 C oracle (plain COO loops, OpenMP) on a bounded sample of
     the same workload: the first `sample_nnz` nonzeros of the shuffled list."""
     from oracle import cpu
@@ -111,11 +111,52 @@ def cpu_baseline(t, Rs, sample_nnz, threads):
                                     return_threads=True)
             total_s += time.perf_counter() - t0
             total_bytes += op_bytes("ttm", Zs, N, R, fib.shape[0], t.dims[m], -(-Zs // 16))
-    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
-            "kind": "oracle",
-            "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
-                      f"every mode, R in {list(Rs)}, float64, {total_s:.2f} s timed "
-                      f"(fibre grouping excluded)"}
+    rec = {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
+           "kind": "oracle",
+           "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
+                     f"every mode, R in {list(Rs)}, float64, {total_s:.2f} s timed "
+                     f"(fibre grouping excluded)"}
+    if cp is not None:
+        R, sweeps, init = cp
+        fits, s_per = cp_oracle(t, R, sweeps, init)
+        rec["cp_als"] = {"R": R, "sweeps": sweeps, "fits": [round(f, 6) for f in fits],
+                         "s_per_iter": round(s_per, 3), "note": "full workload, float64, C MTTKRP loops"}
+    return rec
+
+
+def cp_oracle(t, R, sweeps, init):
+    """The float64 oracle's CP-ALS (Algorithm 1) on the full workload, with
+    the C COO loop for its MTTKRPs, from the same initial factors."""
+    from oracle import cpu, ref
+    vals = t.vals.astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    out = ref.cp_als(t.dims, t.idx, vals, R, [a.astype(np.float64) for a in init], sweeps,
+                     mttkrp=lambda d, i, v, F, n: cpu.mttkrp(d, i, v, F, n))
+    return out["fits"], (time.perf_counter() - t0) / sweeps
+
+
+def cp_gpu(h, t, R, sweeps, init, dtype):
+    """CP-ALS sweeps on the device; wall time of every sweep (each call ends
+    with the 8-byte fit read-back)."""
+    import torch
+    from paper_1705_09905_amd import _lib
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    F = [torch.tensor(a.astype(np.float32), device="cuda").to(tdt).contiguous() for a in init]
+    lam = torch.zeros(R, dtype=torch.float64, device="cuda")
+    grams = torch.zeros((t.order, R, R), dtype=torch.float64, device="cuda")
+    fp = _lib.ptr_array([f.data_ptr() for f in F])
+    fit, used = C.c_double(), C.c_int()
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    code = _lib.FCOO_F32 if dtype == "f32" else _lib.FCOO_BF16
+    fits, secs = [], []
+    torch.cuda.synchronize()
+    for s in range(sweeps):
+        t0 = time.perf_counter()
+        _lib.check(_lib.fcoo_cp_als_iter(h.handle, fp, code, R, lam.data_ptr(), grams.data_ptr(),
+                                         1 if s else 0, C.byref(fit), C.byref(used), stream))
+        secs.append(time.perf_counter() - t0)
+        fits.append(float(fit.value))
+    return fits, secs
 
 
 def load_traffic(khash):
@@ -141,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
+    ap.add_argument("--cp-rank", type=int, default=32)
+    ap.add_argument("--cp-sweeps", type=int, default=10)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -273,11 +316,25 @@ def main():
         "build_s": round(build_s, 2),
         "kernel_hash": khash,
     }
+    # CP-ALS sweeps on the same workload (every mode's MTTKRP build is resident)
+    Rc, Sc = args.cp_rank, args.cp_sweeps
+    init = synth.factors(t.dims, Rc, WORKLOAD_CFG, role="init")
+    cp_rec = {"R": Rc, "sweeps": Sc}
+    for dt in ("f32", "bf16"):
+        fits, secs = cp_gpu(h, t, Rc, Sc, init, dt)
+        cp_rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
+                      "fits": [round(f, 6) for f in fits]}
+    log(f"cp-als f32 {cp_rec['f32']['s_per_iter']} s/iter, bf16 {cp_rec['bf16']['s_per_iter']} s/iter")
+    out["cp_als"] = cp_rec
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         os.environ.setdefault("OMP_PROC_BIND", "close")
         t0 = time.time()
-        out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads)
+        out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads, cp=(Rc, Sc, init))
+        of = out["cpu_baseline"]["cp_als"]["fits"]
+        for dt in ("f32", "bf16"):
+            gf = cp_rec[dt]["fits"]
+            cp_rec[dt]["max_abs_fit_diff_vs_oracle"] = round(max(abs(a - b) for a, b in zip(gf, of)), 6)
         log(f"cpu baseline in {time.time() - t0:.1f}s")
     else:
         out["cpu_baseline"] = None

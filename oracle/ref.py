@@ -384,7 +384,7 @@ def cp_fit(normX2: float, lam: np.ndarray, grams: Sequence[np.ndarray], M_last: 
 
 
 def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
-           storage: str = "f64", tol: float = 0.0):
+           storage: str = "f64", tol: float = 0.0, mttkrp=None):
     """Algorithm 1 for N modes (Gauss-Seidel order, newest factors used).
 
     For each sweep and each mode n:
@@ -396,7 +396,10 @@ def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
     After the last mode the fit is computed (cp_fit).  Stops after `sweeps`
     sweeps, or earlier when tol > 0 and |delta fit| < tol.
     A_0's initial value is never read (line 2 overwrites it first).
+    `mttkrp(dims, idx, vals, factors, n)` may replace mttkrp_coo by another
+    implementation of the same definition (the C loop, for large tensors).
     Returns dict(factors, lam, fits, used_pinv[sweep][mode], grams)."""
+    mttkrp = mttkrp_coo if mttkrp is None else mttkrp
     N = len(dims)
     vals = np.asarray(vals, np.float64)
     normX2 = float(np.sum(vals * vals))
@@ -418,7 +421,7 @@ def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
     for s in range(sweeps):
         used = []
         for n in range(N):
-            M = mttkrp_coo(dims, idx, vals, A, n)
+            M = mttkrp(dims, idx, vals, A, n)
             V = np.ones((R, R))
             for m in range(N):
                 if m != n:

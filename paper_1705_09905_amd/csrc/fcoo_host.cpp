@@ -357,8 +357,9 @@ static int build_device(Built &b, hipStream_t s)
     int64_t acct = 0;
     int rc;
     for (size_t q = 0; q < b.pidx.size(); ++q)
-        if ((rc = upload(&b.d_pidx[q], b.pidx[q].data(), b.nnz, 0, s, &acct))) return rc;
-    if ((rc = upload(&b.d_val, b.val.data(), b.nnz, 0, s, &acct))) return rc;
+        if ((rc = upload(&b.d_pidx[q], b.pidx[q].data(), b.nnz, 4, s, &acct))) return rc;
+    // 4 entries of zero padding: 16-byte stream vectors never read past the allocation
+    if ((rc = upload(&b.d_val, b.val.data(), b.nnz, 4, s, &acct))) return rc;
     {   // bit stream as uint32 words plus two zero words (64-bit windows never read past it)
         const int64_t words = (b.nnz + 31) / 32;
         std::vector<uint32_t> w(words, 0);

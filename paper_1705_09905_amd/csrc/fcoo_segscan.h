@@ -163,6 +163,81 @@ __device__ __forceinline__ uint64_t chunk_heads(const Chunk<U, NPM> &c)
     return c.n >= 64 ? hm : (hm & ((1ull << c.n) - 1ull));
 }
 
+// Stream of a super-chunk of SC = 4 * LPN * K steps, read with 16-byte loads:
+// vector k of lane j holds steps (k * LPN + j) * 4 .. + 3, so each lane
+// group reads whole 16-byte pieces of its run (a full 128-byte line per
+// index array when LPN = 8).  Device streams carry 4 entries of padding, so
+// a vector that starts below the run end never reads past the allocation.
+typedef int int4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef float float4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int K, int NPM>
+struct SChunk {
+    int4a4 idx[K][NPM];
+    float4a4 v[K];
+    uint32_t w0, w1, w2;
+    int sh;
+    int n;
+};
+
+template <int LPN, int SC, int K, int NPM>
+__device__ __forceinline__ void load_schunk(const SegArgs &A, int j, int64_t base, int64_t re,
+                                            SChunk<K, NPM> &c)
+{
+    const int64_t rem = re - base;
+    c.n = rem < SC ? (int)rem : SC;
+    const int64_t p1 = base - 1;
+    const int64_t wi = p1 < 0 ? 0 : (p1 >> 5);
+    c.sh = p1 < 0 ? -1 : (int)(p1 & 31);
+    c.w0 = A.bf[wi];
+    c.w1 = A.bf[wi + 1];
+    c.w2 = A.bf[wi + 2];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int el = (k * LPN + j) * 4;
+        const bool ev = el < c.n;
+        const int64_t e = base + el;
+#pragma unroll
+        for (int qq = 0; qq < NPM; ++qq)
+            c.idx[k][qq] = ev ? __builtin_nontemporal_load(reinterpret_cast<const int4a4 *>(A.pidx[qq] + e))
+                              : int4a4{0, 0, 0, 0};
+        c.v[k] = ev ? __builtin_nontemporal_load(reinterpret_cast<const float4a4 *>(A.vals + e))
+                    : float4a4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+template <int K, int NPM>
+__device__ __forceinline__ uint64_t schunk_heads(const SChunk<K, NPM> &c)
+{
+    const uint64_t lo = (uint64_t)c.w0 | ((uint64_t)c.w1 << 32);
+    const int sh = c.sh < 0 ? 0 : c.sh;
+    const uint64_t x = sh ? ((lo >> sh) | ((uint64_t)c.w2 << (64 - sh))) : lo;
+    const uint64_t top = (c.w2 >> sh) & 1u;
+    const uint64_t cur = c.sh < 0 ? lo : ((x >> 1) | (top << 63));
+    const uint64_t prev = c.sh < 0 ? 0ull : (x & 1ull);
+    const uint64_t hm = cur ^ ((cur << 1) | prev);
+    return c.n >= 64 ? hm : (hm & ((1ull << c.n) - 1ull));
+}
+
+template <int LPN, int ST, int K, int NPM>
+__device__ __forceinline__ int sc_idx(const SChunk<K, NPM> &c, int qq)
+{
+    return bcast_imm<LPN, (ST / 4) % LPN>(c.idx[ST / (4 * LPN)][qq][ST % 4]);
+}
+
+template <int LPN, int ST, int K, int NPM>
+__device__ __forceinline__ float sc_val(const SChunk<K, NPM> &c)
+{
+    return bcast_imm_f<LPN, (ST / 4) % LPN>(c.v[ST / (4 * LPN)][ST % 4]);
+}
+
+template <typename FT, int VW>
+__device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, const Raw<FT, VW> &b,
+                                           Raw<FT, VW> &out)
+{
+    out.v = take_a ? a.v : b.v;
+}
+
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP>
 __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 {
@@ -204,8 +279,21 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)colc * sizeof(FT);
 
     // first chunk of the stream and the tile's segment ordinal: issued first
+    // fast path: 16-byte stream vectors in super-chunks; generic path: chunks
+    constexpr bool FAST = (NP > 0) && (VW > 1);
+    constexpr int CLF = CH0;                                           // gather batch (register budget)
+    constexpr int K = FAST ? ((CLF + 4 * LPN - 1) / (4 * LPN)) : 1;  // vectors per lane per array
+    constexpr int SC = FAST ? 4 * LPN * K : CL;                        // steps per super-chunk
+    static_assert(!FAST || (SC % CLF == 0 && SC <= 64), "super-chunk shape");
+    // SpMTTKRP: consecutive nonzeros often share the first product-mode
+    // index (its order within a segment is sorted); such rows are not re-read
+    constexpr bool REUSE = FAST && ROWMAP && NP >= 2;
     Chunk<U, NPM> cur;
-    if (rs < re) load_chunk<LPN, CL, U, NPM>(A, np, j, rs, re, cur);
+    SChunk<K, NPM> scur;
+    if (rs < re) {
+        if constexpr (FAST) load_schunk<LPN, SC, K, NPM>(A, j, rs, re, scur);
+        else load_chunk<LPN, CL, U, NPM>(A, np, j, rs, re, cur);
+    }
     const int ts0 = A.tile_seg0[tile];
     const int h0 = (int)head_at(A.bf, t0);
 
@@ -275,10 +363,11 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         }
         if (st < n) {
             if constexpr (RESID) {
+                // lanes past R hold column 0 (clamped reads): kept out of the dot product
                 float d = 0.f;
 #pragma unroll
                 for (int k = 0; k < VW; ++k) d += own[k] * h[k];
-                d = group_sum<LPN>(d);
+                d = group_sum<LPN>(cval ? d : 0.f);
                 const float r = d - v;
                 const float sc = r * A.inv_nnz;
 #pragma unroll
@@ -291,39 +380,58 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         }
     };
 
-    for (int64_t base = rs; base < re; base += CL) {
-        Chunk<U, NPM> nxt;
-        const bool more = base + CL < re;
-        if constexpr (CH == CL && NP > 0) {
-            // all rows of the chunk in flight at once
-            Raw<FT, VW> rows[CL][NPM];
-            int gi[CL][NPM];
-            static_for<CL>([&](auto sc) {
-                constexpr int ST = decltype(sc)::value;
-#pragma unroll
-                for (int qq = 0; qq < NPM; ++qq) gi[ST][qq] = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
-            });
-            static_for<CL>([&](auto sc) {
-                constexpr int ST = decltype(sc)::value;
-#pragma unroll
-                for (int qq = 0; qq < NPM; ++qq)
-                    load_raw<FT, VW>(reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)gi[ST][qq] * R4),
-                                     rows[ST][qq]);
-            });
-            if (more) load_chunk<LPN, CL, U, NPM>(A, np, j, base + CL, re, nxt);
-            float vv[CL];
-            static_for<CL>([&](auto sc) {
-                constexpr int ST = decltype(sc)::value;
-                vv[ST] = bcast_imm_f<LPN, ST % LPN>(cur.v[ST / LPN]);
-            });
-            const uint64_t hm = chunk_heads(cur);
-            const int n = cur.n;
-            const bool easy = !RESID && __ballot(hm != 0ull || n < CL) == 0ull;
-            if (easy) {
-                static_for<CL>([&](auto sc) {
+    if constexpr (FAST) {
+        int lastidx = -1;                              // REUSE: index of the row held in last0
+        Raw<FT, VW> last0;
+        set_one<FT, VW>(last0);
+        for (int64_t base = rs; base < re; base += SC) {
+            SChunk<K, NPM> snxt;
+            const bool more = base + SC < re;
+            const uint64_t hms = schunk_heads(scur);
+            const int nsc = scur.n;
+            static_for<SC / CLF>([&](auto cc) {
+                constexpr int C0 = decltype(cc)::value * CLF;
+                // gathers of this chunk, back to back (repeated first-mode rows skipped)
+                Raw<FT, VW> rows[CLF][NPM];
+                uint32_t dup = 0;
+                static_for<CLF>([&](auto sc) {
                     constexpr int ST = decltype(sc)::value;
-                    float h[VW];
-                    to_float<FT, VW>(rows[ST][0], h);
+#pragma unroll
+                    for (int qq = 0; qq < NPM; ++qq) {
+                        const int idx = sc_idx<LPN, C0 + ST, K, NPM>(scur, qq);
+                        const char *p = fb[qq] + (uint64_t)(uint32_t)idx * R4;
+                        if (REUSE && qq == 0) {
+                            const bool d = idx == lastidx;
+                            lastidx = idx;
+                            dup |= (uint32_t)d << ST;
+                            if (!d) load_raw<FT, VW>(reinterpret_cast<const FT *>(p), rows[ST][0]);
+                            else set_one<FT, VW>(rows[ST][0]);
+                        } else {
+                            load_raw<FT, VW>(reinterpret_cast<const FT *>(p), rows[ST][qq]);
+                        }
+                    }
+                });
+                if constexpr (C0 == 0) {
+                    if (more) load_schunk<LPN, SC, K, NPM>(A, j, base + SC, re, snxt);
+                }
+                float vv[CLF];
+                static_for<CLF>([&](auto sc) {
+                    constexpr int ST = decltype(sc)::value;
+                    vv[ST] = sc_val<LPN, C0 + ST, K, NPM>(scur);
+                });
+                const uint64_t hm = (hms >> C0) & ((CLF >= 64) ? ~0ull : ((1ull << CLF) - 1ull));
+                const int n = nsc - C0;
+                const bool easy = !RESID && __ballot(hm != 0ull || n < CLF) == 0ull;
+                auto hrow = [&](auto sc, float (&h)[VW]) {
+                    constexpr int ST = decltype(sc)::value;
+                    if constexpr (REUSE) {
+                        Raw<FT, VW> r0;
+                        select_raw<FT, VW>((dup >> ST) & 1u, last0, rows[ST][0], r0);
+                        last0 = r0;
+                        to_float<FT, VW>(r0, h);
+                    } else {
+                        to_float<FT, VW>(rows[ST][0], h);
+                    }
 #pragma unroll
                     for (int qq = 1; qq < NPM; ++qq) {
                         float x[VW];
@@ -331,25 +439,30 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 #pragma unroll
                         for (int k = 0; k < VW; ++k) h[k] *= x[k];
                     }
+                };
+                if (easy) {
+                    static_for<CLF>([&](auto sc) {
+                        constexpr int ST = decltype(sc)::value;
+                        float h[VW];
+                        hrow(sc, h);
 #pragma unroll
-                    for (int k = 0; k < VW; ++k) acc[k] += vv[ST] * h[k];
-                });
-            } else {
-                static_for<CL>([&](auto sc) {
-                    constexpr int ST = decltype(sc)::value;
-                    float h[VW];
-                    to_float<FT, VW>(rows[ST][0], h);
-#pragma unroll
-                    for (int qq = 1; qq < NPM; ++qq) {
-                        float x[VW];
-                        to_float<FT, VW>(rows[ST][qq], x);
-#pragma unroll
-                        for (int k = 0; k < VW; ++k) h[k] *= x[k];
-                    }
-                    step(h, vv[ST], hm, ST, n);
-                });
-            }
-        } else {
+                        for (int k = 0; k < VW; ++k) acc[k] += vv[ST] * h[k];
+                    });
+                } else {
+                    static_for<CLF>([&](auto sc) {
+                        constexpr int ST = decltype(sc)::value;
+                        float h[VW];
+                        hrow(sc, h);
+                        step(h, vv[ST], hm, ST, n);
+                    });
+                }
+            });
+            scur = snxt;
+        }
+    } else {
+        for (int64_t base = rs; base < re; base += CL) {
+            Chunk<U, NPM> nxt;
+            const bool more = base + CL < re;
             // generic path: gathers in batches of CH steps, runtime mode count
             if (more) load_chunk<LPN, CL, U, NPM>(A, np, j, base + CL, re, nxt);
             const uint64_t hm = chunk_heads(cur);
@@ -384,8 +497,8 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
                     step(h, v, hm, ST, n);
                 });
             });
+            cur = nxt;
         }
-        cur = nxt;
     }
 
     // ---- 3. wave-level segmented scan of the runs' (f, a, b)

@@ -65,7 +65,10 @@ class Tensor:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            L.fcoo_destroy(h)
+            try:
+                L.fcoo_destroy(h)
+            except TypeError:  # interpreter shutdown: the binding is already gone
+                pass
             self._h = C.c_void_p()
 
     @property

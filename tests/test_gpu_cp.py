@@ -36,9 +36,12 @@ def test_gram_matches_numpy(R, dtype):
     np.testing.assert_allclose(G, G.T, rtol=0, atol=1e-9 * np.abs(exp).max())
 
 
-def _run_both(t, R, sweeps, dtype="f32", seed=0):
+def _run_both(t, R, sweeps, dtype="f32", seed=0, dup_column=False):
     P = _lib()
     init = synth.small_factors(t.dims, R, seed=seed)
+    if dup_column:
+        for a in init:
+            a[:, 1] = a[:, 0]
     init_dev = [f32(a) if dtype == "f32" else bf16(a) for a in init]
     h = P.Tensor(t.idx, t.vals, t.dims)
     tag("cp_als", t.dims, t.nnz, "R", R, dtype, "sweeps", sweeps)
@@ -100,12 +103,14 @@ def test_cp_als_rank1_exact_in_one_sweep():
     assert out["fits"][0] > 1 - 1e-3
 
 
-def test_cp_als_pseudo_inverse_when_rank_exceeds_a_dimension():
-    # R = 5 > I_1 = 3: the Gram of mode 1 has rank 3, V is singular for modes 0 and 2
-    t = synth.random_small([20, 3, 15], 600, seed=6)
-    out, orc = _run_both(t, 5, 4)
-    tag("pinv flags", out["used_pinv"], [p for p in orc["used_pinv"]])
-    assert any(out["used_pinv"])
+def test_cp_als_pseudo_inverse_on_singular_normal_equations():
+    # columns 0 and 1 equal in every factor: every Gram, hence V, has two equal
+    # rows, and the update keeps them equal, so each mode needs V^+
+    t = synth.random_small([20, 12, 15], 800, seed=6)
+    out, orc = _run_both(t, 5, 4, dup_column=True)
+    tag("pinv flags", out["used_pinv"], orc["used_pinv"])
+    assert all(all(p) for p in orc["used_pinv"])
+    assert out["used_pinv"] == [0b111] * 4
     assert np.abs(np.array(out["fits"]) - np.array(orc["fits"])).max() <= 1e-3
 
 

@@ -36,7 +36,8 @@ def test_model_at_nnz(dims, Z, R):
 
 @pytest.mark.parametrize("dims,Z,R", [([60, 50, 40], 20000, 16), ([30, 20, 10, 8], 6000, 8),
                                        ([1, 300, 200], 30000, 32), ([50, 40, 30], 8000, 64),
-                                       ([40, 30, 20], 5000, 5)])
+                                       ([40, 30, 20], 5000, 5), ([40, 30, 20], 5000, 12),
+                                       ([40, 30, 20], 5000, 48)])
 def test_resid_spmttkrp_and_loss(dims, Z, R):
     P = _P()
     import torch
