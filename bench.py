@@ -159,8 +159,22 @@ def cp_gpu(h, t, R, sweeps, init, dtype):
     return fits, secs
 
 
+def kernel_symbol(op, R, N):
+    """Demangled name of the tile-kernel instantiation that runs (op, R)
+    with float32 factors (16-byte lanes: 4 columns per lane)."""
+    lanes = (R + 3) // 4
+    lpn = 1
+    while lpn < lanes:
+        lpn *= 2
+    lpn = min(lpn, 16)
+    np_ = (N - 1) if op == "mttkrp" else 1
+    npt = np_ if np_ <= 3 else 0
+    return (f"void fcoo::dev::seg_tile_kernel<float, 4, {lpn}, {npt}, false, "
+            f"{'true' if op == 'mttkrp' else 'false'}>(fcoo::dev::SegArgs)")
+
+
 def load_traffic(khash):
-    p = os.path.join(ROOT, "profiles", "traffic_spmttkrp_zipf20M_r32.json")
+    p = os.path.join(ROOT, "profiles", "traffic_tile_kernel_zipf20M.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -182,6 +196,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4_000_000)
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 256 MiB device copy first (scales traffic counters)")
     ap.add_argument("--cp-rank", type=int, default=32)
     ap.add_argument("--cp-sweeps", type=int, default=10)
     args = ap.parse_args()
@@ -198,6 +214,12 @@ def main():
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
 
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     Rs = [int(r) for r in args.ranks.split(",")]
     t0 = time.time()
     t = synth.config_tensor(WORKLOAD_CFG, nnz=args.nnz or None)
@@ -283,11 +305,17 @@ def main():
     tr = load_traffic(khash)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": (tr["bytes_per_launch"] if tr else None),
+                "traffic": None,
                 "kernel": f"seg_tile_kernel ({'SpMTTKRP' if dom[0] == 'mttkrp' else 'SpTTM'}, R={dom[1]}, "
                           f"float32, per-mode launch)",
+                "symbol": kernel_symbol(dom[0], dom[1], t.order),
                 "bytes_per_launch": int(dc["bytes"] / dc["n"]),
                 "avg_launch_ms": round(dc["ms"] / dc["n"], 4)}
+    if tr is not None:
+        rec = tr.get("kernels", {}).get(roofline["symbol"])
+        if rec is not None:
+            roofline["traffic"] = rec["bytes_per_launch"]
+            roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     value = step_bytes / (ms_per_step / 1e3) / 1e9
     mt = {R: classes[("mttkrp", R)] for R in Rs}
     tt = {R: classes[("ttm", R)] for R in Rs}

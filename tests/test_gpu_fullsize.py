@@ -1,0 +1,63 @@
+"""Parity at the benchmark's full size and launch configuration: the Zipf(1.1)
+100,000 x 80,000 x 60,000 tensor with 20M nonzeros, SpMTTKRP and SpTTM in
+every mode at R = 16 and 32 (threadlen 16, tile 4096), against the float64 C
+oracle computing every output row; plus CP-ALS sweeps (float32 and bfloat16
+factors) against the oracle's fits on the same tensor."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cpu, ref
+
+from conftest import gpu_available
+from gpu_util import TOL_BF16, TOL_F32, f32, from_dev, rel_fro, tag, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def c2():
+    tag("generating the 20M-nonzero Zipf workload")
+    return synth.config_tensor(1)
+
+
+def test_full_size_spmttkrp_spttm_all_modes(c2):
+    from paper_1705_09905_amd import Tensor
+    t = c2
+    h = Tensor(t.idx, t.vals, t.dims)
+    vals = f32(t.vals)
+    for m in range(3):
+        h.build(m, "mttkrp", threadlen=16, tile_nnz=4096)
+        h.build(m, "ttm", threadlen=16, tile_nnz=4096)
+    for R in (16, 32):
+        F = [f32(f) for f in synth.factors(t.dims, R, 1)]
+        Fd = [to_dev(f) for f in F]
+        for m in range(3):
+            tag("full size mttkrp", m, "R", R)
+            M = from_dev(h.spmttkrp(m, Fd))
+            err = rel_fro(M, cpu.mttkrp(t.dims, t.idx, vals, F, m))
+            tag("rel err", err)
+            assert err <= TOL_F32
+            tag("full size ttm", m, "R", R)
+            fib, Y = cpu.ttm(t.dims, t.idx, vals, F[m], m)
+            Yd = from_dev(h.spttm(m, Fd[m]))
+            assert Yd.shape == Y.shape
+            err = rel_fro(Yd, Y)
+            tag("rel err", err)
+            assert err <= TOL_F32
+
+
+def test_full_size_cp_als_f32_and_bf16(c2):
+    from paper_1705_09905_amd import Tensor, cp_als
+    t = c2
+    R, sweeps = 16, 4
+    init = synth.factors(t.dims, R, 1, role="init")
+    orc = ref.cp_als(t.dims, t.idx, f32(t.vals), R, [f32(a) for a in init], sweeps,
+                     mttkrp=lambda d, i, v, F, n: cpu.mttkrp(d, i, v, F, n))
+    h = Tensor(t.idx, t.vals, t.dims)
+    for dtype, tol in (("f32", 1e-3), ("bf16", 1e-3)):
+        out = cp_als(h, R, sweeps, [f32(a) for a in init], dtype=dtype)
+        d = np.abs(np.array(out["fits"]) - np.array(orc["fits"])).max()
+        tag("cp-als", dtype, out["fits"], "oracle", orc["fits"], "max diff", d)
+        assert d <= tol
