@@ -184,8 +184,106 @@ def load_traffic(khash):
     return d
 
 
+EXTRA_WORKLOADS = {
+    # name: (workload index in synth.CONFIGS, rank, kind)
+    "cpals-order4-zipf50M": (2, 32, "cpals"),
+    "cpals-planted100M": (3, 16, "cpals"),
+    "gradcp-zipf200M": (4, 64, "gradcp"),
+}
+
+
+def run_extra(args, log):
+    """CP-ALS (ten sweeps, float32 and bfloat16 factors) or gradient-based CP
+    (fused residual SpMTTKRP steps with Adam) on one of the large workloads.
+    Prints one JSON line; value = float32 seconds per sweep / per step."""
+    import torch
+    import synth
+    from paper_1705_09905_amd import CPMSELoss, Tensor
+    cfg, R, kind = EXTRA_WORKLOADS[args.workload]
+    t0 = time.time()
+    t = synth.config_tensor(cfg)
+    log(f"generated {t.name} Z={t.nnz} in {time.time() - t0:.1f}s")
+    h = Tensor(t.idx, t.vals, t.dims)
+    t0 = time.time()
+    for m in range(t.order):
+        h.build(m, "mttkrp", threadlen=args.threadlen, tile_nnz=args.tile)
+    build_s = time.time() - t0
+    infos = [h.info(m) for m in range(t.order)]
+    N = t.order
+    init = synth.factors(t.dims, R, cfg, role="init")
+    rec = {"metric": METRIC, "n_gpus": 1, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic", "build_s": round(build_s, 2),
+           "config": {"workload": f"{t.name}: " + ("CP-ALS" if kind == "cpals" else "gradient CP (MSE, Adam)")
+                      + f", R = {R}", "dims": t.dims, "nnz": t.nnz, "R": R,
+                      "threadlen": args.threadlen, "tile_nnz": args.tile}}
+
+    def mttkrp_bytes(sf, own=False):
+        b = 0
+        for m in range(N):
+            b += op_bytes("mttkrp", t.nnz, N, R, infos[m]["nseg"], t.dims[m], infos[m]["npart"], sf)
+            if own:
+                b += t.dims[m] * R * sf
+        return b
+
+    if kind == "cpals":
+        sweeps = args.cp_sweeps
+        rec["sweeps"] = sweeps
+        for dt in ("f32", "bf16"):
+            fits, secs = cp_gpu(h, t, R, sweeps, init, dt)
+            s_it = float(np.median(secs[1:] if len(secs) > 1 else secs))
+            B = mttkrp_bytes(4 if dt == "f32" else 2)
+            rec[dt] = {"s_per_iter": round(s_it, 6), "fits": [round(f, 6) for f in fits],
+                       "spmttkrp_bytes_per_sweep": B, "GBps_spmttkrp_bytes": round(B / s_it / 1e9, 1)}
+            log(f"cp-als {dt}: {s_it * 1e3:.3f} ms/sweep, fits {rec[dt]['fits']}")
+        rec["value"], rec["unit"], rec["dtype"] = rec["f32"]["s_per_iter"], "s/iter", "f32"
+        if not args.no_cpu:
+            fits, s_per = cp_oracle(t, R, sweeps, init)
+            threads = len(os.sched_getaffinity(0))
+            rec["cpu_baseline"] = {"value": round(s_per, 3), "unit": "s/iter", "cores": threads,
+                                   "kind": "oracle", "fits": [round(f, 6) for f in fits],
+                                   "sample": f"full workload, {sweeps} sweeps, float64, C MTTKRP loops"}
+            for dt in ("f32", "bf16"):
+                rec[dt]["max_abs_fit_diff_vs_oracle"] = round(
+                    max(abs(a - b) for a, b in zip(rec[dt]["fits"], fits)), 6)
+    else:
+        steps, warm = args.steps, args.warmup
+        rec["steps"], rec["warmup"] = steps, warm
+        for dt in ("f32", "bf16"):
+            masters = [torch.tensor(a.astype(np.float32), device="cuda").requires_grad_() for a in init]
+            opt = torch.optim.Adam(masters, lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+            losses = []
+
+            def step():
+                opt.zero_grad()
+                loss = CPMSELoss.apply(h, dt, *masters)
+                loss.backward()
+                opt.step()
+                return loss
+
+            for _ in range(warm):
+                losses.append(step())
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                losses.append(step())
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            B = mttkrp_bytes(4 if dt == "f32" else 2, own=True)
+            rec[dt] = {"ms_per_step": round(ms, 4), "losses": [round(float(x), 6) for x in losses],
+                       "fused_resid_bytes_per_step": B, "GBps_fused_resid_bytes": round(B / ms / 1e6, 1)}
+            log(f"gradient CP {dt}: {ms:.3f} ms/step")
+        rec["value"], rec["unit"], rec["dtype"] = rec["f32"]["ms_per_step"] / 1e3, "s/step", "f32"
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="zipf20M", choices=["zipf20M"] + list(EXTRA_WORKLOADS),
+                    help="zipf20M: the SpMTTKRP/SpTTM bench (default); the others time CP-ALS or "
+                         "gradient CP on a large workload")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
@@ -213,6 +311,10 @@ def main():
 
     def log(*a):
         print("[bench]", *a, file=sys.stderr, flush=True)
+
+    if args.workload != "zipf20M":
+        run_extra(args, log)
+        return
 
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")

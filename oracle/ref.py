@@ -10,6 +10,7 @@ Sarwate, Mehri Dehnavi), written slowly and in float64:
 
 * matricization, Kronecker and Khatri-Rao products      -- Sec. II, Eq. (1)-(2)
 * TTM / SpTTM                                           -- Sec. II, Eq. (3)
+* TTMc / SpTTMc (Kronecker rows)                        -- Sec. II, Eq. (4), Table I
 * MTTKRP / SpMTTKRP (dense and COO forms)               -- Sec. II, Eq. (5)-(6)
 * mode roles (index / product modes)                    -- Sec. IV-A, Table I
 * F-COO encoding (product indices, val, bf, sf)         -- Sec. IV-B, Fig. 2, Table II
@@ -173,6 +174,58 @@ def ttm_dense_rows(X: np.ndarray, U: np.ndarray, n: int, fibres: np.ndarray) -> 
     """Rows of the dense TTM result read at the listed fibres."""
     Yd = ttm_dense(X, U, n)
     return np.stack([Yd[tuple(f)] for f in fibres]) if len(fibres) else np.zeros((0, U.shape[1]))
+
+
+# ----------------------------------------------------------------------------
+# Sec. II, Eq. (4) and Table I (third row): SpTTMc, the tensor times a chain
+# of matrices on every mode but one (the kernel of Tucker / HOOI)
+# ----------------------------------------------------------------------------
+
+def ttmc_width(factors: Sequence[np.ndarray], n: int) -> int:
+    """Columns of Y_(n): the product of the ranks of the modes other than n."""
+    w = 1
+    for m, U in enumerate(factors):
+        if m != n:
+            w *= int(np.asarray(U).shape[1])
+    return w
+
+
+def ttmc_coo(dims, idx, vals, factors, n, chunk: int = 1 << 16) -> np.ndarray:
+    """Eq. (4) generalised to N modes: for every nonzero e,
+    Y_(n)[i_n(e), :] += vals[e] * (U_{m_1}[i_{m_1}(e), :] kron U_{m_2}[i_{m_2}(e), :] kron ...)
+    with m_1 < m_2 < ... the modes other than n (the product modes of Table I)
+    and kron the Kronecker product of Eq. (1) applied to 1 x R_m rows, so the
+    column of (p_1, p_2, ...) is (..(p_1 R_{m_2} + p_2) R_{m_3} + ..): the last
+    product mode's column runs fastest.  factors[m] is I_m x R_m; factors[n]
+    is not read.  Rows with no nonzero stay zero.  Returns I_n x prod R_m."""
+    N = len(dims)
+    pm = [m for m in range(N) if m != n]
+    W = ttmc_width(factors, n)
+    Y = np.zeros((int(dims[n]), W), dtype=np.float64)
+    vals = np.asarray(vals, np.float64)
+    for s0 in range(0, len(vals), chunk):
+        s1 = min(len(vals), s0 + chunk)
+        h = vals[s0:s1, None]
+        for m in pm:
+            rows = np.asarray(factors[m], np.float64)[np.asarray(idx[m][s0:s1], np.int64)]
+            # row-wise Eq. (1): block p of (h kron u) is h_p * u
+            h = (h[:, :, None] * rows[:, None, :]).reshape(s1 - s0, -1)
+        np.add.at(Y, np.asarray(idx[n][s0:s1], np.int64), h)
+    return Y
+
+
+def ttmc_dense(X: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
+    """TTMc as a chain of dense TTMs (Eq. 3): contract every mode m != n of X
+    with U_m (one mode at a time), then lay the result out as Y_(n) with the
+    column order of Eq. (4) (later product modes fastest)."""
+    N = X.ndim
+    Y = np.asarray(X, np.float64)
+    # contract from the highest mode down so the remaining axis numbers stay put
+    for m in reversed(range(N)):
+        if m != n:
+            Y = np.moveaxis(np.tensordot(Y, np.asarray(factors[m], np.float64), axes=([m], [0])), -1, m)
+    Y = np.moveaxis(Y, n, 0)
+    return Y.reshape(Y.shape[0], -1)
 
 
 # ----------------------------------------------------------------------------
