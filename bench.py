@@ -298,6 +298,7 @@ def main():
                     help="run a plain 256 MiB device copy first (scales traffic counters)")
     ap.add_argument("--cp-rank", type=int, default=32)
     ap.add_argument("--cp-sweeps", type=int, default=10)
+    ap.add_argument("--ttmc-rank", type=int, default=16, help="SpTTMc rank per mode (0: skip)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -446,6 +447,39 @@ def main():
         "build_s": round(build_s, 2),
         "kernel_hash": khash,
     }
+    # SpTTMc (Kronecker rows, Eq. 4) on the same SpMTTKRP builds: R per mode,
+    # output dims[m] x R^(N-1); timed apart from the step (not in `value`)
+    Rk = args.ttmc_rank
+    if Rk > 0:
+        Fk = [torch.tensor(f.astype(np.float32), device=dev) for f in synth.factors(t.dims, Rk, WORKLOAD_CFG)]
+        W = Rk ** (N - 1)
+        yk = {m: torch.empty((t.dims[m], W), dtype=torch.float32, device=dev) for m in range(N)}
+        fk = {m: [None if k == m else Fk[k] for k in range(N)] for m in range(N)}
+        for m in range(N):
+            h.spttmc(m, fk[m], out=yk[m])
+        ev = HipEvents()
+        kp = []
+        for _ in range(max(3, args.steps // 4)):
+            for m in range(N):
+                a, b = ev.new(), ev.new()
+                _lib.check(_lib.fcoo_set_tile_events(h.handle, a, b))
+                h.spttmc(m, fk[m], out=yk[m])
+                kp.append((m, a, b))
+        torch.cuda.synchronize()
+        _lib.check(_lib.fcoo_set_tile_events(h.handle, None, None))
+        km = {m: float(np.mean([ev.ms(a, b) for mm, a, b in kp if mm == m])) for m in range(N)}
+        ev.close()
+        kb = {}
+        for m in range(N):
+            inf = infos[("mttkrp", m)]
+            flags = (t.nnz + 7) // 8 + 4 * ((inf["npart"] + 31) // 32)
+            kb[m] = (4 * t.nnz * N + flags + 4 * inf["nseg"] + t.nnz * (N - 1) * Rk * 4
+                     + 4 * t.dims[m] * W)
+        out["spttmc"] = {"R_per_mode": Rk, "width": W,
+                         "tile_ms_per_mode": [round(km[m], 4) for m in range(N)],
+                         "GBps_per_mode": [round(kb[m] / km[m] / 1e6, 1) for m in range(N)],
+                         "GFLOPs_per_mode": [round(t.nnz * W * N / km[m] / 1e6, 1) for m in range(N)]}
+        log(f"spttmc R={Rk}: {out['spttmc']['tile_ms_per_mode']} ms")
     # CP-ALS sweeps on the same workload (every mode's MTTKRP build is resident)
     Rc, Sc = args.cp_rank, args.cp_sweeps
     init = synth.factors(t.dims, Rc, WORKLOAD_CFG, role="init")

@@ -169,6 +169,27 @@ int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtyp
 int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float *Y, void *stream);
 
 /*
+ * fcoo_spttmc -- tensor times a matrix chain on every mode but `mode` (Eq. 4,
+ * Table I third row; the kernel of Tucker / HOOI), Y = Y_(mode):
+ *   Y[i, c] = sum over nonzeros e with i_mode(e) = i of
+ *             val(e) * U_{m1}[i_m1(e), p_1] * U_{m2}[i_m2(e), p_2] * ...
+ *   where m1 < m2 < ... are the other modes and column c is the Kronecker
+ *   (Eq. 1) position of (p_1, p_2, ...): the last mode's column runs fastest,
+ *   c = (..(p_1 ranks[m2] + p_2) ranks[m3] + ..).
+ *   factors  host array of N device pointers; factors[m] is dims[m] x
+ *            ranks[m] of `dtype`; factors[mode] is not read (may be NULL).
+ *   ranks    host array of N ints, each in [1, 256]; ranks[mode] is ignored;
+ *            the width W = prod_{m != mode} ranks[m] must not exceed 16384.
+ *   Y        device, dims[mode] x W float32, written fully (rows of empty
+ *            slices are written as 0).
+ * Uses the SpMTTKRP encoding of the mode (the index and product modes are the
+ * same): requires fcoo_build(mode, FCOO_OP_MTTKRP).  Deterministic.
+ * Errors: as fcoo_spmttkrp.
+ */
+int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype, const int *ranks,
+                float *Y, void *stream);
+
+/*
  * fcoo_spmttkrp_values -- fcoo_spmttkrp with the tensor's values replaced
  * by `g` (device, Z float32 in the caller's input order of fcoo_create):
  *   M[i, r] = sum_{e : i_mode(e) = i} g[e] prod_{m != mode} A_m[i_m(e), r].

@@ -75,6 +75,7 @@ _SIGS = {
     "fcoo_export": (_i, [_vp, _i, _i, C.POINTER(_vp), _vp, _vp, _vp, _vp, _vp, _vp]),
     "fcoo_spmttkrp": (_i, [_vp, _i, C.POINTER(_vp), _i, _i, _vp, _vp]),
     "fcoo_spttm": (_i, [_vp, _i, _vp, _i, _i, _vp, _vp]),
+    "fcoo_spttmc": (_i, [_vp, _i, C.POINTER(_vp), _i, C.POINTER(_i), _vp, _vp]),
     "fcoo_spmttkrp_values": (_i, [_vp, _i, _vp, C.POINTER(_vp), _i, _i, _vp, _vp]),
     "fcoo_model_at_nnz": (_i, [_vp, C.POINTER(_vp), _i, _i, _vp, _vp]),
     "fcoo_resid_spmttkrp": (_i, [_vp, _i, C.POINTER(_vp), _i, _i, _vp, _vp, _vp]),

@@ -32,6 +32,8 @@ SOURCES = [
     "seg_bf16.hip",
     "seg_f32_resid.hip",
     "seg_bf16_resid.hip",
+    "seg_f32_kron.hip",
+    "seg_bf16_kron.hip",
 ]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]

@@ -565,6 +565,44 @@ int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtyp
     return launch_segmented(p, s, false);
 }
 
+int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype, const int *ranks,
+                float *Y, void *stream)
+{
+    clear_error();
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
+    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    if (!ranks) return fail(FCOO_EINVAL, "ranks is NULL");
+    int64_t W = 1;
+    for (int m = 0; m < t->order; ++m) {
+        if (m == mode) continue;
+        if (ranks[m] < 1 || ranks[m] > kMaxR)
+            return fail(FCOO_EUNSUPPORTED, "ranks[%d] = %d outside [1, %d]", m, ranks[m], kMaxR);
+        W *= ranks[m];
+        if (W > kMaxKronWidth)
+            return fail(FCOO_EUNSUPPORTED, "SpTTMc width (product of the ranks) above %d", kMaxKronWidth);
+    }
+    int rc = check_factors(t, mode, factors, dtype, 1);
+    if (rc) return rc;
+    if (!Y) return fail(FCOO_EINVAL, "Y is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    TileProblem p{};
+    p.b = b;
+    p.kron = true;
+    for (size_t q = 0; q < b->pmodes.size(); ++q) {
+        p.fac[q] = factors[b->pmodes[q]];
+        p.kr[q] = ranks[b->pmodes[q]];
+    }
+    p.vals = b->d_val;
+    p.dtype = dtype;
+    p.R = (int)W;
+    p.out = Y;
+    if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * W, s))) return rc;
+    p.carry = b->d_carry;
+    p.ev_before = t->ev_before;
+    p.ev_after = t->ev_after;
+    return launch_segmented(p, s, false);
+}
+
 int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float *Y, void *stream)
 {
     clear_error();

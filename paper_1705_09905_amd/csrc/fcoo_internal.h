@@ -13,6 +13,7 @@ namespace fcoo {
 
 constexpr int kMaxOrder = 8;
 constexpr int kMaxR = 256;
+constexpr int kMaxKronWidth = 16384;   // SpTTMc output columns (prod of the product-mode ranks)
 constexpr int kBlock = 256;        // threads per workgroup of the tile kernels (4 waves)
 
 // error reporting (thread-local message, negative code returned)
@@ -125,6 +126,9 @@ struct TileProblem {
     double *partial = nullptr;       // per-tile partial losses (ntiles) or null
     hipEvent_t ev_before = nullptr;  // recorded around the tile kernel when set
     hipEvent_t ev_after = nullptr;
+    // SpTTMc: Kronecker rows; R is then the output width prod kr[q]
+    bool kron = false;
+    int kr[kMaxOrder] = {};          // per product mode q: columns of its factor
 };
 int launch_segmented(const TileProblem &p, hipStream_t s, bool resid);
 int launch_permute_values(const Built &b, const float *g, float *out, hipStream_t s);

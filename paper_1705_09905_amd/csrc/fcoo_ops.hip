@@ -20,6 +20,16 @@ __global__ __launch_bounds__(256) void fixup_kernel(const int32_t *__restrict__ 
     const int64_t e = blockIdx.x;
     const int tb = fix[3 * e], ta = fix[3 * e + 1], row = fix[3 * e + 2];
     const int tid = threadIdx.x;
+    if (R > 256) {
+        // wide rows (SpTTMc): one column per thread, the chain summed in order
+        for (int c = tid; c < R; c += 256) {
+            float v = cb[(int64_t)ta * R + c];
+            for (int64_t t = (int64_t)ta + 1; t < tb; ++t) v += ca[t * R + c];
+            if (tb < ntiles) v += ca[(int64_t)tb * R + c];
+            out[(int64_t)row * R + c] = v;
+        }
+        return;
+    }
     const int slots = 256 / R;
     const int slot = tid / R, c = tid - (tid / R) * R;
     float s = 0.f;
@@ -167,10 +177,17 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.nseg = (int)b.nseg;
         a.inv_nnz = p.inv_nnz;
         const int V = p.dtype == FCOO_F32 ? 4 : 8;
-        L.vec = (R % V) == 0;
+        // a lane's VW columns must lie in one row piece of the (last) factor
+        L.vec = ((p.kron ? p.kr[np - 1] : R) % V) == 0;
         const int VW = L.vec ? V : 1;
         int lpn = next_pow2((R + VW - 1) / VW);
-        if (L.vec && lpn > 16) lpn = 16;
+        if (p.kron) {
+            for (int q = 0; q < np; ++q) a.kr[q] = p.kr[q];
+            if (lpn < 4) lpn = 4;
+            if (lpn > 64) lpn = 64;
+        } else if (L.vec && lpn > 16) {
+            lpn = 16;
+        }
         if (!L.vec) lpn = 64;
         L.lpn = lpn;
         const int rt = lpn * VW;
@@ -182,7 +199,8 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         L.grid = dim3((unsigned)b.ntiles, (unsigned)nrt, 1);
         hipError_t e;
         if (p.ev_before) FCOO_HIP(hipEventRecord(p.ev_before, s));
-        if (p.dtype == FCOO_F32) e = resid ? seg_launch_f32_resid(L, s) : seg_launch_f32(L, s);
+        if (p.kron) e = p.dtype == FCOO_F32 ? seg_launch_f32_kron(L, s) : seg_launch_bf16_kron(L, s);
+        else if (p.dtype == FCOO_F32) e = resid ? seg_launch_f32_resid(L, s) : seg_launch_f32(L, s);
         else e = resid ? seg_launch_bf16_resid(L, s) : seg_launch_bf16(L, s);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
         if (p.ev_after) FCOO_HIP(hipEventRecord(p.ev_after, s));

@@ -11,7 +11,7 @@ namespace fcoo {
 struct SegLaunch {
     dev::SegArgs args;
     bool vec;        // 16-byte row chunks per lane (R a multiple of the vector width)
-    int lpn;         // lanes per nonzero: 1, 2, 4, 8, 16 (vector) or 64 (scalar)
+    int lpn;         // lanes per nonzero: 1, 2, 4, 8, 16 (vector; SpTTMc up to 64) or 64 (scalar)
     int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
     bool rowmap;     // output row = seg_row[segment] (SpMTTKRP) or the segment ordinal (SpTTM)
     dim3 grid;
@@ -21,6 +21,14 @@ template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP>
 static hipError_t seg_go(const SegLaunch &L, hipStream_t s)
 {
     hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, RESID, ROWMAP>), L.grid, dim3(256), 0, s,
+                       L.args);
+    return hipGetLastError();
+}
+
+template <typename FT, int VW, int LPN, int NP>
+static hipError_t seg_go_k(const SegLaunch &L, hipStream_t s)
+{
+    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, false, true, true>), L.grid, dim3(256), 0, s,
                        L.args);
     return hipGetLastError();
 }
@@ -59,9 +67,38 @@ static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
     }
 }
 
+// SpTTMc: Kronecker rows (generic path), output row = seg_row[segment].
+// Lanes per nonzero: 4 .. 64 (vector) or 64 (scalar); product modes 2, 3 or
+// a runtime count.
+template <typename FT, int VW, int LPN>
+static hipError_t seg_np_kron(const SegLaunch &L, hipStream_t s)
+{
+    switch (L.npt) {
+        case 2: return seg_go_k<FT, VW, LPN, 2>(L, s);
+        case 3: return seg_go_k<FT, VW, LPN, 3>(L, s);
+        default: return seg_go_k<FT, VW, LPN, 0>(L, s);
+    }
+}
+
+template <typename FT>
+static hipError_t seg_dispatch_kron(const SegLaunch &L, hipStream_t s)
+{
+    constexpr int V = dev::Elem<FT>::VEC;
+    if (!L.vec) return seg_go_k<FT, 1, 64, 0>(L, s);
+    switch (L.lpn) {
+        case 4: return seg_np_kron<FT, V, 4>(L, s);
+        case 8: return seg_np_kron<FT, V, 8>(L, s);
+        case 16: return seg_np_kron<FT, V, 16>(L, s);
+        case 32: return seg_np_kron<FT, V, 32>(L, s);
+        default: return seg_np_kron<FT, V, 64>(L, s);
+    }
+}
+
 hipError_t seg_launch_f32(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_bf16(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_f32_resid(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_bf16_resid(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_f32_kron(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_bf16_kron(const SegLaunch &L, hipStream_t s);
 
 }  // namespace fcoo

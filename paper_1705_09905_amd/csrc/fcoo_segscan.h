@@ -31,6 +31,13 @@
 //   f = fX | fY,  a = fX ? aX : aX + aY,  b = fY ? bY : bX + aY,
 // and the segment closed at Y's first start is complete (started inside the
 // combined range) iff fX, with value bX + aY.
+//
+// SpTTMc (Eq. 4, Table I third row) uses the SpMTTKRP encoding of its mode
+// and the same scan; only the per-nonzero product changes: output column c
+// of a row is a digit tuple (p_1, .., p_k) over the product modes (the last
+// runs fastest) and takes val * U_1(i_1, p_1) * .. * U_k(i_k, p_k).  A lane
+// owns VW consecutive columns inside one block of the last mode, so it
+// gathers one element of every other mode's row and VW of the last one.
 #pragma once
 
 #include "fcoo_device.h"
@@ -59,6 +66,7 @@ struct SegArgs {
     int tile_nnz;
     int nseg;                        // number of segments
     float inv_nnz;                   // RESID: 1 / Z
+    int kr[kMaxNP];                  // KRON: columns of each product mode's factor (R = their product)
 };
 
 template <int N, int I = 0, class F>
@@ -238,7 +246,7 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
     out.v = take_a ? a.v : b.v;
 }
 
-template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP>
+template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false>
 __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
@@ -274,13 +282,33 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     const int np = NP > 0 ? NP : A.np;
     const uint64_t R4 = (uint64_t)R * sizeof(FT);
     const char *fb[NPM];
+    uint64_t R4k[NPM];                                // KRON: row bytes of each product mode
+    if constexpr (KRON) {
+        // digits of this lane's first column, last product mode fastest
+        int rem = colc;
 #pragma unroll
-    for (int qq = 0; qq < NPM; ++qq)
-        fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)colc * sizeof(FT);
+        for (int qq = NPM - 1; qq >= 0; --qq) {
+            if (qq < np) {
+                const int d = rem % A.kr[qq];
+                rem /= A.kr[qq];
+                fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)d * sizeof(FT);
+                R4k[qq] = (uint64_t)A.kr[qq] * sizeof(FT);
+            } else {
+                fb[qq] = nullptr;
+                R4k[qq] = 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int qq = 0; qq < NPM; ++qq) {
+            fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)colc * sizeof(FT);
+            R4k[qq] = R4;
+        }
+    }
 
     // first chunk of the stream and the tile's segment ordinal: issued first
     // fast path: 16-byte stream vectors in super-chunks; generic path: chunks
-    constexpr bool FAST = (NP > 0) && (VW > 1);
+    constexpr bool FAST = (NP > 0) && (VW > 1) && !KRON;
     constexpr int CLF = CH0;                                           // gather batch (register budget)
     constexpr int K = FAST ? ((CLF + 4 * LPN - 1) / (4 * LPN)) : 1;  // vectors per lane per array
     constexpr int SC = FAST ? 4 * LPN * K : CL;                        // steps per super-chunk
@@ -470,16 +498,20 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
             static_for<CL / CH>([&](auto sbc) {
                 constexpr int S0 = decltype(sbc)::value * CH;
                 Raw<FT, VW> rows[CH][NPM];
+                Raw<FT, 1> ks[CH][NPM];                 // KRON: one element of each non-last mode
                 static_for<CH>([&](auto jjc) {
                     constexpr int ST = S0 + decltype(jjc)::value;
 #pragma unroll
                     for (int qq = 0; qq < NPM; ++qq) {
                         const int idx = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
-                        if (qq < np)
-                            load_raw<FT, VW>(reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * R4),
-                                             rows[ST - S0][qq]);
-                        else
-                            set_one<FT, VW>(rows[ST - S0][qq]);
+                        const FT *p = reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * R4k[qq]);
+                        if constexpr (KRON) {
+                            if (qq < np - 1) load_raw<FT, 1>(p, ks[ST - S0][qq]);
+                            else if (qq == np - 1) load_raw<FT, VW>(p, rows[ST - S0][0]);
+                        } else {
+                            if (qq < np) load_raw<FT, VW>(p, rows[ST - S0][qq]);
+                            else set_one<FT, VW>(rows[ST - S0][qq]);
+                        }
                     }
                 });
                 static_for<CH>([&](auto jjc) {
@@ -487,12 +519,26 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
                     const float v = bcast_imm_f<LPN, ST % LPN>(cur.v[ST / LPN]);
                     float h[VW];
                     to_float<FT, VW>(rows[ST - S0][0], h);
+                    if constexpr (KRON) {
+                        float m = 1.f;
 #pragma unroll
-                    for (int qq = 1; qq < NPM; ++qq) {
-                        float x[VW];
-                        to_float<FT, VW>(rows[ST - S0][qq], x);
+                        for (int qq = 0; qq < NPM - 1; ++qq) {
+                            if (qq < np - 1) {
+                                float x[1];
+                                to_float<FT, 1>(ks[ST - S0][qq], x);
+                                m *= x[0];
+                            }
+                        }
 #pragma unroll
-                        for (int k = 0; k < VW; ++k) h[k] *= x[k];
+                        for (int k = 0; k < VW; ++k) h[k] *= m;
+                    } else {
+#pragma unroll
+                        for (int qq = 1; qq < NPM; ++qq) {
+                            float x[VW];
+                            to_float<FT, VW>(rows[ST - S0][qq], x);
+#pragma unroll
+                            for (int k = 0; k < VW; ++k) h[k] *= x[k];
+                        }
                     }
                     step(h, v, hm, ST, n);
                 });

@@ -155,6 +155,39 @@ class Tensor:
                              _stream()))
         return out
 
+    def spttmc(self, mode: int, factors, out=None):
+        """Y_(mode) = X times every other factor (Eq. 4): row i, column
+        (p_1, p_2, ..) in Kronecker order (later modes fastest) holds
+        sum val * U_m1[i_m1, p_1] * U_m2[i_m2, p_2] * ..  (float32,
+        dims[mode] x prod of the other factors' column counts).  Factors may
+        differ in column count; they share one dtype.  Uses the SpMTTKRP
+        build of the mode."""
+        torch = _torch()
+        if len(factors) != self.order:
+            raise ValueError(f"need {self.order} factors (use None for the skipped mode)")
+        ptrs, ranks, dt, W = [], [], None, 1
+        for m, f in enumerate(factors):
+            if m == mode:
+                ptrs.append(0)
+                ranks.append(1)
+                continue
+            if not isinstance(f, torch.Tensor) or not f.is_cuda:
+                raise TypeError(f"factor {m} must be a CUDA torch tensor")
+            if f.dim() != 2 or f.shape[0] != self.dims[m] or not f.is_contiguous():
+                raise ValueError(f"factor {m} must be a contiguous {self.dims[m]} x R_{m} matrix")
+            code = _dtype_code(f)
+            dt = code if dt is None else dt
+            if code != dt:
+                raise ValueError("factors differ in dtype")
+            ptrs.append(f.data_ptr())
+            ranks.append(int(f.shape[1]))
+            W *= int(f.shape[1])
+        if out is None:
+            out = torch.empty((self.dims[mode], W), dtype=torch.float32, device="cuda")
+        rk = (C.c_int * self.order)(*ranks)
+        L.check(L.fcoo_spttmc(self._h, int(mode), L.ptr_array(ptrs), dt, rk, out.data_ptr(), _stream()))
+        return out
+
     def spmttkrp_values(self, mode: int, g, factors, out=None):
         """SpMTTKRP with the values replaced by g (float32, input order)."""
         torch = _torch()

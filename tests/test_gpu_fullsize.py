@@ -61,3 +61,28 @@ def test_full_size_cp_als_f32_and_bf16(c2):
         d = np.abs(np.array(out["fits"]) - np.array(orc["fits"])).max()
         tag("cp-als", dtype, out["fits"], "oracle", orc["fits"], "max diff", d)
         assert d <= tol
+
+
+def test_full_size_spttmc_sampled_rows(c2):
+    # SpTTMc at R = 16 per mode (256 Kronecker columns) on the full tensor;
+    # the oracle computes a sample of output rows: the three longest slices
+    # and 40 seeded others (each row only needs its own slice's nonzeros)
+    from paper_1705_09905_amd import Tensor
+    t = c2
+    h = Tensor(t.idx, t.vals, t.dims)
+    vals = f32(t.vals)
+    F = [f32(f) for f in synth.factors(t.dims, 16, 1)]
+    Fd = [to_dev(f) for f in F]
+    g = np.random.default_rng(12)
+    for m in range(3):
+        h.build(m, "mttkrp", threadlen=16, tile_nnz=4096)
+        tag("full size spttmc", m)
+        Y = from_dev(h.spttmc(m, [None if k == m else Fd[k] for k in range(3)]))
+        counts = np.bincount(t.idx[m], minlength=t.dims[m])
+        rows = np.unique(np.concatenate([np.argsort(counts)[-3:], g.choice(t.dims[m], 40, replace=False)]))
+        sel = np.isin(t.idx[m], rows)
+        sub_idx = [i[sel] for i in t.idx]
+        exp = ref.ttmc_coo(t.dims, sub_idx, vals[sel], F, m)[rows]
+        err = rel_fro(Y[rows], exp)
+        tag("rel err", err, "rows", len(rows), "nnz", int(sel.sum()))
+        assert err <= TOL_F32
