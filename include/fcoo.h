@@ -225,8 +225,10 @@ int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, in
 /*
  * fcoo_cp_als_iter -- one sweep of CP-ALS (Algorithm 1, N modes, Gauss-Seidel):
  * for n = 0..N-1: M = SpMTTKRP_n; V = Hadamard product of the Grams G_m,
- * m != n (float64); A_n = M V^-1 (float64 Cholesky; symmetric-eigen
- * pseudo-inverse when V is not positive definite); lambda = column 2-norms
+ * m != n (float64); A_n = M V^-1 (float64 inverse by elimination whose
+ * pivots are those of the Cholesky factorisation; symmetric-eigen
+ * pseudo-inverse when a pivot is <= 0 or below 1e-13 max diag V, R <= 64);
+ * lambda = column 2-norms
  * of A_n; A_n columns divided by lambda (zero columns left zero); A_n stored
  * as `dtype` (round to nearest even); G_n = A_n^T A_n of the stored values.
  * Then fit = 1 - sqrt(max(0, |X|^2 + |Xhat|^2 - 2 <X, Xhat>)) / |X|.
@@ -236,7 +238,11 @@ int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, in
  *            `grams_valid` = 0 to have them computed from the factors first.
  *   fit      host double* (out); the call waits for it.
  *   used_pinv host int* or NULL (out): bit n set if mode n used the pseudo-inverse.
- * Requires fcoo_build(n, FCOO_OP_MTTKRP) for every mode n.
+ * Requires fcoo_build(n, FCOO_OP_MTTKRP) for every mode n.  The R x R solve
+ * of each mode runs on a second stream owned by the handle, beside that
+ * mode's SpMTTKRP (it needs only the other modes' Grams); events order it
+ * after the earlier work on `stream` and before the row solve, so for the
+ * caller all the work is ordered on `stream`.
  * Errors: FCOO_EINVAL, FCOO_ENOTBUILT, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
  */
 int fcoo_cp_als_iter(fcoo_tensor *t, void *const *factors, int dtype, int R, double *lambda,

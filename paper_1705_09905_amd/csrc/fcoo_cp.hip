@@ -4,9 +4,10 @@
 //
 // Per mode n of a sweep: M = SpMTTKRP_n (segmented-scan kernels);
 // V = Hadamard product of the Grams G_m, m != n (float64);
-// W = V^-1 by Cholesky (V = L L^T, W = L^-T L^-1), or the pseudo-inverse
-// from a symmetric eigendecomposition (cyclic Jacobi) when V is not
-// numerically positive definite; A_n = M W with column 2-norms lambda,
+// W = V^-1 by Gauss-Jordan elimination (its pivots are the squared pivots of
+// the Cholesky factorisation V = L L^T), or the pseudo-inverse from a
+// symmetric eigendecomposition (cyclic Jacobi) when V is not numerically
+// positive definite; A_n = M W with column 2-norms lambda,
 // A_n / lambda stored as float32 or bfloat16 (round to nearest even);
 // G_n = A_n^T A_n from the stored values.  After the last mode:
 // fit = 1 - sqrt(max(0, |X|^2 + |Xhat|^2 - 2 <X, Xhat>)) / |X|, with
@@ -30,7 +31,8 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 // Partial Gram of rows [blk * kGramRows, ...) for the 32 x 32 tile pair
 // (tr, tc): each wave accumulates its quarter of the rows on the matrix
 // cores (float32 inputs: 32x32x2; bfloat16: 32x32x8), the four waves are
-// summed in float64 and written to partial[blk][R x R].
+// summed in float64 and written to partial[blk][R x R].  The operands of the
+// next GU matrix steps are loaded while the current ones run.
 template <typename FT>
 __global__ __launch_bounds__(256) void gram_partial_kernel(const FT *__restrict__ A, int64_t I, int R,
                                                            double *__restrict__ partial)
@@ -44,28 +46,57 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const FT *__restrict_
     int64_t r1 = r0 + kGramRows / 4;
     if (r1 > I) r1 = I;
     const int ca = tr * 32 + (lane & 31), cb = tc * 32 + (lane & 31);
+    const bool va = ca < R, vb = cb < R;
     const int kk = lane >> 5;
     floatx16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    constexpr int GU = 8;                                    // matrix steps per operand batch
     if constexpr (sizeof(FT) == 4) {
-        for (int64_t i = r0; i < r1; i += 2) {
-            const int64_t row = i + kk;
-            const float a = (row < r1 && ca < R) ? reinterpret_cast<const float *>(A)[row * R + ca] : 0.f;
-            const float b = (row < r1 && cb < R) ? reinterpret_cast<const float *>(A)[row * R + cb] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        const float *Af = reinterpret_cast<const float *>(A);
+        constexpr int STEP = 2 * GU;                         // rows per batch
+        auto ld = [&](int64_t i, float (&a)[GU], float (&b)[GU]) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int64_t row = i + 2 * u + kk;
+                a[u] = (row < r1 && va) ? Af[row * R + ca] : 0.f;
+                b[u] = (row < r1 && vb) ? Af[row * R + cb] : 0.f;
+            }
+        };
+        float a0[GU], b0v[GU];
+        ld(r0, a0, b0v);
+        for (int64_t i = r0; i < r1; i += STEP) {
+            float a1[GU], b1[GU];
+            ld(i + STEP, a1, b1);
+#pragma unroll
+            for (int u = 0; u < GU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[u], b0v[u], acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < GU; ++u) { a0[u] = a1[u]; b0v[u] = b1[u]; }
         }
     } else {
         const uint16_t *Ab = reinterpret_cast<const uint16_t *>(A);
-        for (int64_t i = r0; i < r1; i += 8) {
-            shortx4 a, b;
+        constexpr int GB = GU / 2;
+        constexpr int STEP = 8 * GB;
+        auto ld = [&](int64_t i, shortx4 (&a)[GB], shortx4 (&b)[GB]) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int64_t row = i + 4 * kk + t;
-                a[t] = (short)((row < r1 && ca < R) ? Ab[row * R + ca] : 0);
-                b[t] = (short)((row < r1 && cb < R) ? Ab[row * R + cb] : 0);
+            for (int u = 0; u < GB; ++u) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int64_t row = i + 8 * u + 4 * kk + t;
+                    a[u][t] = (short)((row < r1 && va) ? Ab[row * R + ca] : 0);
+                    b[u][t] = (short)((row < r1 && vb) ? Ab[row * R + cb] : 0);
+                }
             }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        };
+        shortx4 a0[GB], b0v[GB];
+        ld(r0, a0, b0v);
+        for (int64_t i = r0; i < r1; i += STEP) {
+            shortx4 a1[GB], b1[GB];
+            ld(i + STEP, a1, b1);
+#pragma unroll
+            for (int u = 0; u < GB; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a0[u], b0v[u], acc, 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < GB; ++u) { a0[u] = a1[u]; b0v[u] = b1[u]; }
         }
     }
     // accumulator v of lane l holds tile element (8 (v/4) + 4 (l/32) + v%4, l%32)
@@ -82,26 +113,30 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const FT *__restrict_
     }
 }
 
-// out[e] = scale * sum_b partial[b][e], e < n_per, b in order.
-__global__ __launch_bounds__(256) void sum_blocks_kernel(const double *__restrict__ partial, int64_t nblk,
-                                                         int64_t n_per, double *__restrict__ out)
+// out[e] = sum_b partial[b][e] (b < nblk): one wave per element, lane t sums
+// b = t, t + 64, ..., then a butterfly; fixed order, so repeatable.
+__global__ __launch_bounds__(64) void sum_blocks_kernel(const double *__restrict__ partial, int64_t nblk,
+                                                        int64_t n_per, double *__restrict__ out)
 {
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_per; e += (int64_t)gridDim.x * 256) {
-        double s = 0.0;
-        for (int64_t b = 0; b < nblk; ++b) s += partial[b * n_per + e];
-        out[e] = s;
-    }
+    const int64_t e = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += 64) s += partial[b * n_per + e];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) out[e] = s;
 }
 
-// One workgroup: V = Hadamard of the Grams but mode n; W = V^-1 (Cholesky)
-// or V^+ (cyclic Jacobi eigendecomposition) when a Cholesky pivot is <= 0
-// or below 1e-13 * max(diag V).  flags[n] = 1 when the pseudo-inverse was
-// used.  R <= kMaxCpR.  V lives in LDS (the Cholesky factor overwrites its
-// lower triangle); tmp (R x R, global) holds L^-1 or the eigenvectors.
+// One workgroup: V = Hadamard of the Grams but mode n; W = V^-1 by
+// Gauss-Jordan elimination without row exchanges (lane k of each wave owns
+// column k, the four waves share its rows; the pivots are the
+// Schur-complement diagonal, i.e. the squared Cholesky pivots of V = L L^T), or V^+ from a cyclic Jacobi eigendecomposition when
+// a pivot is <= 0 or below 1e-13 * max(diag V).  flags[n] = 1 when the
+// pseudo-inverse was used.  R <= kMaxCpR.  V is inverted in place in LDS;
+// the Jacobi fallback keeps its eigenvectors in tmp (global, R x R).
 __device__ void form_hadamard(const double *__restrict__ grams, int N, int n, int R,
                               double (*V)[kMaxCpR + 1])
 {
-    for (int e = threadIdx.x; e < R * R; e += 256) {
+    for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
         double h = 1.0;
         for (int m = 0; m < N; ++m)
             if (m != n) h *= grams[(int64_t)m * R * R + e];
@@ -114,54 +149,51 @@ __global__ __launch_bounds__(256) void als_solve_kernel(const double *__restrict
                                                         double *__restrict__ tmp, int *__restrict__ flags)
 {
     __shared__ double V[kMaxCpR][kMaxCpR + 1];
-    __shared__ double dmax_s, cs_s[2];
-    __shared__ int fail_s;
+    __shared__ double rj[kMaxCpR], cj[kMaxCpR];
+    __shared__ double cs_s[2];
     const int tid = threadIdx.x;
+    const int k = tid & 63;                         // column of this lane
+    const int q = tid >> 6;                         // rows q, q + 4, q + 8, ... of that column
     form_hadamard(grams, N, n, R, V);
     __syncthreads();
-    if (tid == 0) {
-        double d = 0.0;
-        for (int i = 0; i < R; ++i) d = V[i][i] > d ? V[i][i] : d;
-        dmax_s = d;
-        fail_s = 0;
-    }
-    __syncthreads();
-    // Cholesky in place (lower triangle), column by column
+    double dmax = 0.0;
+    for (int i = 0; i < R; ++i) dmax = V[i][i] > dmax ? V[i][i] : dmax;
+    bool fail = false;
+    constexpr int RPL = kMaxCpR / 4;                // rows per lane at most
     for (int j = 0; j < R; ++j) {
-        if (tid == 0) {
-            double sj = V[j][j];
-            for (int k = 0; k < j; ++k) sj -= V[j][k] * V[j][k];
-            if (!(sj > 0.0) || sj <= 1e-13 * dmax_s) fail_s = 1;
-            else V[j][j] = sqrt(sj);
+        const double p = V[j][j];                   // Schur-complement pivot (same on every lane)
+        if (!(p > 0.0) || p <= 1e-13 * dmax) { fail = true; break; }
+        if (tid < R) {
+            rj[tid] = V[j][tid];
+            cj[tid] = V[tid][j];
         }
         __syncthreads();
-        if (fail_s) break;
-        for (int i = j + 1 + tid; i < R; i += 256) {
-            double si = V[i][j];
-            for (int k = 0; k < j; ++k) si -= V[i][k] * V[j][k];
-            V[i][j] = si / V[j][j];
-        }
-        __syncthreads();
-    }
-    if (!fail_s) {
-        // tmp = L^-1 (lower triangular): column c solves L x = e_c
-        for (int c = tid; c < R; c += 256) {
-            for (int i = 0; i < R; ++i) {
-                if (i < c) { tmp[i * R + c] = 0.0; continue; }
-                double si = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) si -= V[i][k] * tmp[k * R + c];
-                tmp[i * R + c] = si / V[i][i];
+        const double ip = 1.0 / p;
+        if (k < R) {
+            const double rjk = rj[k] * ip;
+            // rows i != j: a - c_i rjk (column j: -c_i / p); row j is set below
+            double a[RPL], c[RPL];
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+                const int i = q + 4 * u;
+                const int ic = i < R ? i : 0;
+                a[u] = V[ic][k];
+                c[u] = cj[ic];
+            }
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+                const int i = q + 4 * u;
+                const double t = a[u] - c[u] * rjk;
+                const double tc = -c[u] * ip;
+                if (i < R) V[i][k] = k == j ? tc : t;
             }
         }
         __syncthreads();
-        // W = L^-T L^-1
-        for (int e = tid; e < R * R; e += 256) {
-            const int i = e / R, j = e % R;
-            const int k0 = i > j ? i : j;
-            double se = 0.0;
-            for (int k = k0; k < R; ++k) se += tmp[k * R + i] * tmp[k * R + j];
-            W[e] = se;
-        }
+        if (tid < R) V[j][tid] = tid == j ? ip : rj[tid] * ip;
+        __syncthreads();
+    }
+    if (!fail) {
+        for (int e = tid; e < R * R; e += 256) W[e] = V[e / R][e % R];
         if (tid == 0) flags[n] = 0;
         return;
     }
@@ -222,13 +254,10 @@ __global__ __launch_bounds__(256) void als_solve_kernel(const double *__restrict
         __syncthreads();
         if (done) break;
     }
-    if (tid == 0) {
-        double d = 0.0;
-        for (int i = 0; i < R; ++i) d = V[i][i] > d ? V[i][i] : d;
-        dmax_s = d;
-    }
+    double dm = 0.0;
+    for (int i = 0; i < R; ++i) dm = V[i][i] > dm ? V[i][i] : dm;
+    const double cut = (double)R * 2.220446049250313e-16 * dm;
     __syncthreads();
-    const double cut = (double)R * 2.220446049250313e-16 * dmax_s;
     for (int e = tid; e < R * R; e += 256) {
         const int i = e / R, j = e % R;
         double se = 0.0;
@@ -241,74 +270,102 @@ __global__ __launch_bounds__(256) void als_solve_kernel(const double *__restrict
     if (tid == 0) flags[n] = 1;
 }
 
-// Pass 1 of the row solve: per block of rows, sum_i (M W)(i, c)^2 in float64.
-// Thread layout: 256 / RC row slots x RC columns (RC = R rounded up to a
-// power of two, R <= kMaxCpR).
-__global__ __launch_bounds__(256) void rowsolve_norm_kernel(const float *__restrict__ M,
-                                                            const double *__restrict__ W, int64_t I,
-                                                            int R, int RC, int rows_per_block,
-                                                            double *__restrict__ partial)
-{
-    __shared__ double red[256];
-    const int slots = 256 / RC;
-    const int slot = threadIdx.x / RC, c = threadIdx.x % RC;
-    const int64_t b0 = (int64_t)blockIdx.x * rows_per_block;
-    int64_t b1 = b0 + rows_per_block;
-    if (b1 > I) b1 = I;
-    double ss = 0.0;
-    if (c < R) {
-        for (int64_t i = b0 + slot; i < b1; i += slots) {
-            const float *m = M + i * R;
-            double y = 0.0;
-            for (int k = 0; k < R; ++k) y += (double)m[k] * W[k * R + c];
-            ss += y * y;
-        }
-    }
-    red[threadIdx.x] = ss;
-    __syncthreads();
-    if (threadIdx.x < R) {
-        double s = 0.0;
-        for (int k = 0; k < slots; ++k) s += red[k * RC + threadIdx.x];
-        partial[(int64_t)blockIdx.x * R + threadIdx.x] = s;
-    }
-}
 
-__global__ void lambda_kernel(const double *__restrict__ partial, int64_t nblk, int R,
-                              double *__restrict__ lambda)
-{
-    const int c = threadIdx.x;
-    if (c >= R) return;
-    double s = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) s += partial[b * R + c];
-    lambda[c] = sqrt(s);
-}
-
+// Row solve, Y = M W (I x R, float64 accumulation), in row tiles staged in
+// LDS with W.  Lane layout: 256 / RC row slots x RC columns (RC = R rounded
+// up to a power of two, R <= kMaxCpR); a tile has RPT rows per slot.
+//   STORE = false: per block, the column sums of Y^2 -> partial[blk][R];
+//   STORE = true:  A(i, c) = Y(i, c) / lambda_c (0 when lambda_c = 0), stored
+//                  as FT (bfloat16: round to nearest even).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 {
     const uint32_t u = __float_as_uint(f);
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// Pass 2: A(i, c) = (M W)(i, c) / lambda_c (0 when lambda_c = 0), stored as FT.
-template <typename FT>
-__global__ __launch_bounds__(256) void rowsolve_store_kernel(const float *__restrict__ M,
-                                                             const double *__restrict__ W,
-                                                             const double *__restrict__ lambda, int64_t I,
-                                                             int R, int RC, FT *__restrict__ A)
+template <int RC> struct RowTile {
+    static constexpr int SLOTS = 256 / RC;
+    static constexpr int RPT = RC >= 4 ? RC / 4 : 1;          // rows per slot per tile
+    static constexpr int ROWS = SLOTS * RPT;                  // rows per tile (64 .. 256)
+};
+
+template <typename FT, int RC, bool STORE>
+__global__ __launch_bounds__(256) void rowsolve_kernel(const float *__restrict__ M, const double *__restrict__ W,
+                                                       const double *__restrict__ lambda, int64_t I, int R,
+                                                       int tiles_per_block, double *__restrict__ partial,
+                                                       FT *__restrict__ A)
 {
-    const int slots = 256 / RC;
-    const int slot = threadIdx.x / RC, c = threadIdx.x % RC;
-    if (c >= R) return;
-    const double lam = lambda[c];
-    for (int64_t i = (int64_t)blockIdx.x * slots + slot; i < I; i += (int64_t)gridDim.x * slots) {
-        const float *m = M + i * R;
-        double y = 0.0;
-        for (int k = 0; k < R; ++k) y += (double)m[k] * W[k * R + c];
-        const double a = lam > 0.0 ? y / lam : 0.0;
-        if constexpr (sizeof(FT) == 4) reinterpret_cast<float *>(A)[i * R + c] = (float)a;
-        else reinterpret_cast<uint16_t *>(A)[i * R + c] = f32_to_bf16_rne((float)a);
+    using RT = RowTile<RC>;
+    __shared__ double sW[RC * RC];
+    __shared__ float sM[RT::ROWS * (RC + 1)];
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const int slot = tid / RC, c = tid % RC;
+    for (int e = tid; e < RC * RC; e += 256) {
+        const int k = e / RC, cc = e % RC;
+        sW[e] = (k < R && cc < R) ? W[k * R + cc] : 0.0;
+    }
+    const double lam = (STORE && c < R) ? lambda[c] : 0.0;
+    double ss = 0.0;
+    const int64_t first = (int64_t)blockIdx.x * tiles_per_block * RT::ROWS;
+    for (int tt = 0; tt < tiles_per_block; ++tt) {
+        const int64_t i0 = first + (int64_t)tt * RT::ROWS;
+        if (i0 >= I) break;
+        const int nrow = I - i0 < RT::ROWS ? (int)(I - i0) : RT::ROWS;
+        __syncthreads();                                   // sW written / previous tile consumed
+        for (int e = tid; e < nrow * R; e += 256) sM[(e / R) * (RC + 1) + e % R] = M[i0 * R + e];
+        __syncthreads();
+        double y[RT::RPT];
+#pragma unroll
+        for (int u = 0; u < RT::RPT; ++u) y[u] = 0.0;
+        for (int k = 0; k < R; ++k) {
+            const double wk = sW[k * RC + c];
+#pragma unroll
+            for (int u = 0; u < RT::RPT; ++u) y[u] += (double)sM[(u * RT::SLOTS + slot) * (RC + 1) + k] * wk;
+        }
+#pragma unroll
+        for (int u = 0; u < RT::RPT; ++u) {
+            const int r = u * RT::SLOTS + slot;
+            if (r < nrow && c < R) {
+                if constexpr (STORE) {
+                    const double a = lam > 0.0 ? y[u] / lam : 0.0;
+                    const int64_t o = (i0 + r) * R + c;
+                    if constexpr (sizeof(FT) == 4) reinterpret_cast<float *>(A)[o] = (float)a;
+                    else reinterpret_cast<uint16_t *>(A)[o] = f32_to_bf16_rne((float)a);
+                } else {
+                    ss += y[u] * y[u];
+                }
+            }
+        }
+    }
+    if constexpr (!STORE) {
+        red[tid] = ss;
+        __syncthreads();
+        if (tid < R) {
+            double s = 0.0;
+            for (int k = 0; k < RT::SLOTS; ++k) s += red[k * RC + tid];
+            partial[(int64_t)blockIdx.x * R + tid] = s;
+        }
     }
 }
+
+// lambda_c = sqrt(sum_b partial[b][c]): one workgroup per column, fixed order.
+__global__ __launch_bounds__(256) void lambda_kernel(const double *__restrict__ partial, int64_t nblk, int R,
+                                                     double *__restrict__ lambda)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < nblk; b += 256) s += partial[b * R + c];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lambda[c] = sqrt(red[0]);
+}
+
 
 // Fit, pass 1: per block, sum_i sum_r lambda_r M(i, r) A(i, r) in float64.
 template <typename FT>
@@ -385,6 +442,37 @@ static int pow2_ceil(int x)
     return p;
 }
 
+// Rows per row-solve tile for RC = R rounded up to a power of two.
+static int rowsolve_rows(int RC)
+{
+    switch (RC) {
+        case 1: return dev::RowTile<1>::ROWS;
+        case 2: return dev::RowTile<2>::ROWS;
+        case 4: return dev::RowTile<4>::ROWS;
+        case 8: return dev::RowTile<8>::ROWS;
+        case 16: return dev::RowTile<16>::ROWS;
+        case 32: return dev::RowTile<32>::ROWS;
+        default: return dev::RowTile<64>::ROWS;
+    }
+}
+
+template <typename FT, bool STORE>
+static hipError_t rowsolve_launch(int RC, int nblk, hipStream_t s, const float *M, const double *W,
+                                  const double *lambda, int64_t I, int R, double *partial, FT *A)
+{
+    const dim3 g((unsigned)nblk), b(256);
+    switch (RC) {
+        case 1: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 1, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        case 2: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 2, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        case 4: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 4, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        case 8: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 8, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        case 16: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 16, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        case 32: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 32, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+        default: hipLaunchKernelGGL((dev::rowsolve_kernel<FT, 64, STORE>), g, b, 0, s, M, W, lambda, I, R, 1, partial, A); break;
+    }
+    return hipGetLastError();
+}
+
 // G = A^T A (float64) of an I x R factor; partials in ws->dbl.
 static int gram_launch(fcoo_tensor *t, const void *A, int dtype, int64_t I, int R, double *G, hipStream_t s)
 {
@@ -399,7 +487,7 @@ static int gram_launch(fcoo_tensor *t, const void *A, int dtype, int64_t I, int 
         hipLaunchKernelGGL(dev::gram_partial_kernel<dev::bf16raw>, dim3(nblk, ntile * ntile), dim3(256), 0, s,
                            (const dev::bf16raw *)A, I, R, t->ws.dbl);
     FCOO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dev::sum_blocks_kernel, dim3(ceil_div((int64_t)R * R, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(dev::sum_blocks_kernel, dim3((unsigned)((int64_t)R * R)), dim3(64), 0, s,
                        t->ws.dbl, (int64_t)nblk, (int64_t)R * R, G);
     FCOO_HIP(hipGetLastError());
     return FCOO_OK;
@@ -438,15 +526,16 @@ int fcoo_cp_als_iter(fcoo_tensor *t, void *const *factors, int dtype, int R, dou
     int64_t maxI = 0;
     for (int n = 0; n < N; ++n) maxI = t->dims[n] > maxI ? t->dims[n] : maxI;
     if ((rc = ensure_device_floats(&t->ws.M, &t->ws.M_cap, maxI * R, s))) return rc;
-    // scratch doubles: W (R*R) + lambda partials / inner partials + gram partials
-    const int rows_pb = 4096;
-    const int64_t nblk_max = ceil_div(maxI, rows_pb) + 1;
+    // scratch doubles: gram partials | W | tmp | block partials | fit
+    const int RC = pow2_ceil(R);
+    const int rows_tile = rowsolve_rows(RC);
+    const int inner_rows = R < 8192 ? 8192 / R : 1;              // rows per fit-partial block
+    const int64_t nblk_max = ceil_div(maxI, rows_tile < inner_rows ? rows_tile : inner_rows) + 1;
     const int64_t gram_need = (int64_t)ceil_div(maxI, dev::kGramRows) * R * R + 16;
     const int64_t need = 2 * (int64_t)R * R + nblk_max * R + 64 + gram_need;
     if ((rc = ensure_device_doubles(&t->ws.dbl, &t->ws.dbl_cap, need, s))) return rc;
     if (!t->ws.flags) FCOO_HIP(hipMalloc((void **)&t->ws.flags, 16 * sizeof(int)));
     if (!t->ws.host_pinned) FCOO_HIP(hipHostMalloc((void **)&t->ws.host_pinned, 64, hipHostMallocDefault));
-    // layout of ws.dbl: [gram partials | W | block partials | fit]
     double *Wd = t->ws.dbl + gram_need;
     double *tmpd = Wd + (int64_t)R * R;
     double *part = tmpd + (int64_t)R * R;
@@ -456,37 +545,44 @@ int fcoo_cp_als_iter(fcoo_tensor *t, void *const *factors, int dtype, int R, dou
         for (int m = 0; m < N; ++m)
             if ((rc = gram_launch(t, factors[m], dtype, t->dims[m], R, grams + (int64_t)m * R * R, s))) return rc;
 
-    const int RC = pow2_ceil(R);
+    // V_n needs only the Grams of the other modes, which are final before
+    // SpMTTKRP_n starts: the solve runs on a second stream beside it
+    if (!t->aux) {
+        FCOO_HIP(hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking));
+        FCOO_HIP(hipEventCreateWithFlags(&t->ev_dep, hipEventDisableTiming));
+        FCOO_HIP(hipEventCreateWithFlags(&t->ev_solved, hipEventDisableTiming));
+    }
     for (int n = 0; n < N; ++n) {
         const int64_t I = t->dims[n];
-        if ((rc = fcoo_spmttkrp(t, n, (const void *const *)factors, dtype, R, t->ws.M, stream))) return rc;
-        hipLaunchKernelGGL(dev::als_solve_kernel, dim3(1), dim3(256), 0, s, grams, N, n, R, Wd, tmpd,
+        FCOO_HIP(hipEventRecord(t->ev_dep, s));
+        FCOO_HIP(hipStreamWaitEvent(t->aux, t->ev_dep, 0));
+        hipLaunchKernelGGL(dev::als_solve_kernel, dim3(1), dim3(256), 0, t->aux, grams, N, n, R, Wd, tmpd,
                            t->ws.flags);
         FCOO_HIP(hipGetLastError());
-        const int nblk = ceil_div(I, rows_pb);
-        hipLaunchKernelGGL(dev::rowsolve_norm_kernel, dim3(nblk), dim3(256), 0, s, t->ws.M, Wd, I, R, RC,
-                           rows_pb, part);
+        FCOO_HIP(hipEventRecord(t->ev_solved, t->aux));
+        if ((rc = fcoo_spmttkrp(t, n, (const void *const *)factors, dtype, R, t->ws.M, stream))) return rc;
+        FCOO_HIP(hipStreamWaitEvent(s, t->ev_solved, 0));
+        const int nblk = ceil_div(I, rows_tile);
+        hipError_t e = rowsolve_launch<float, false>(RC, nblk, s, t->ws.M, Wd, nullptr, I, R, part, nullptr);
+        if (e != hipSuccess) return hip_fail(e, "row solve (norms)");
+        hipLaunchKernelGGL(dev::lambda_kernel, dim3(R), dim3(256), 0, s, part, (int64_t)nblk, R, lambda);
         FCOO_HIP(hipGetLastError());
-        hipLaunchKernelGGL(dev::lambda_kernel, dim3(1), dim3(kMaxR), 0, s, part, (int64_t)nblk, R, lambda);
-        FCOO_HIP(hipGetLastError());
-        const int sgrid = ceil_div(I, 256 / RC) < 65535 * 4 ? ceil_div(I, 256 / RC) : 65535 * 4;
         if (dtype == FCOO_F32)
-            hipLaunchKernelGGL(dev::rowsolve_store_kernel<float>, dim3(sgrid), dim3(256), 0, s, t->ws.M, Wd,
-                               lambda, I, R, RC, (float *)factors[n]);
+            e = rowsolve_launch<float, true>(RC, nblk, s, t->ws.M, Wd, lambda, I, R, nullptr, (float *)factors[n]);
         else
-            hipLaunchKernelGGL(dev::rowsolve_store_kernel<dev::bf16raw>, dim3(sgrid), dim3(256), 0, s, t->ws.M,
-                               Wd, lambda, I, R, RC, (dev::bf16raw *)factors[n]);
-        FCOO_HIP(hipGetLastError());
+            e = rowsolve_launch<dev::bf16raw, true>(RC, nblk, s, t->ws.M, Wd, lambda, I, R, nullptr,
+                                                    (dev::bf16raw *)factors[n]);
+        if (e != hipSuccess) return hip_fail(e, "row solve (store)");
         if ((rc = gram_launch(t, factors[n], dtype, I, R, grams + (int64_t)n * R * R, s))) return rc;
     }
     const int64_t IN = t->dims[N - 1];
-    const int nblk = ceil_div(IN, rows_pb);
+    const int nblk = ceil_div(IN, inner_rows);
     if (dtype == FCOO_F32)
         hipLaunchKernelGGL(dev::inner_kernel<float>, dim3(nblk), dim3(256), 0, s, t->ws.M,
-                           (const float *)factors[N - 1], lambda, IN, R, rows_pb, part);
+                           (const float *)factors[N - 1], lambda, IN, R, inner_rows, part);
     else
         hipLaunchKernelGGL(dev::inner_kernel<dev::bf16raw>, dim3(nblk), dim3(256), 0, s, t->ws.M,
-                           (const dev::bf16raw *)factors[N - 1], lambda, IN, R, rows_pb, part);
+                           (const dev::bf16raw *)factors[N - 1], lambda, IN, R, inner_rows, part);
     FCOO_HIP(hipGetLastError());
     hipLaunchKernelGGL(dev::fit_kernel, dim3(1), dim3(256), 0, s, part, (int64_t)nblk, grams, N, R, lambda,
                        t->normX2, fitd);

@@ -535,6 +535,9 @@ void fcoo_destroy(fcoo_tensor *t)
     for (auto &p : t->d_coo) if (p) hipFree(p);
     if (t->d_coo_val) hipFree(t->d_coo_val);
     t->ws.free_all();
+    if (t->ev_dep) hipEventDestroy(t->ev_dep);
+    if (t->ev_solved) hipEventDestroy(t->ev_solved);
+    if (t->aux) hipStreamDestroy(t->aux);
     delete t;
 }
 

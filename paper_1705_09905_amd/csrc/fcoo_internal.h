@@ -101,6 +101,9 @@ struct fcoo_tensor {
 
     // optional events recorded around each tile kernel (caller-owned)
     hipEvent_t ev_before = nullptr, ev_after = nullptr;
+    // CP-ALS: second stream for the R x R solve (default priority), created on first use
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_dep = nullptr, ev_solved = nullptr;
 };
 
 namespace fcoo {
