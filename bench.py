@@ -292,7 +292,7 @@ def main():
     ap.add_argument("--threadlen", type=int, default=16)
     ap.add_argument("--tile", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (scales traffic counters)")

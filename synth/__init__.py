@@ -17,6 +17,8 @@ so a given (config, role) always yields the same numbers.
 from __future__ import annotations
 
 import dataclasses
+import os
+import sys
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -122,7 +124,9 @@ def _unique_coords(dims, nnz, draw_batch, g_sel) -> List[np.ndarray]:
     while keys.shape[0] < nnz:
         batch = max(1024, int(1.15 * (nnz - keys.shape[0])) + 64)
         cols = draw_batch(batch)
+        _note("drew", batch, "coordinates")
         keys = np.unique(np.concatenate([keys, _pack(cols, dims)]))
+        _note("unique", keys.shape[0], "of", nnz)
         want = nnz
     if keys.shape[0] > want:
         keep = np.sort(g_sel.choice(keys.shape[0], size=want, replace=False))
@@ -192,6 +196,7 @@ def planted_values(idx: List[np.ndarray], planted: List[np.ndarray], noise_var: 
     sigma = sqrt(noise_var))."""
     nnz = idx[0].shape[0]
     out = np.empty(nnz, dtype=np.float64)
+    _note("planting values, rank", planted[0].shape[1])
     for s in range(0, nnz, chunk):
         e = min(nnz, s + chunk)
         p = planted[0][idx[0][s:e]].copy()
@@ -220,11 +225,39 @@ CONFIGS = {
 }
 
 
+def _note(*parts):
+    # generation steps of the large workloads take tens of seconds each
+    if os.environ.get("FCOO_SYNTH_VERBOSE") == "1":
+        print("[synth]", *parts, file=sys.stderr, flush=True)
+
+
 def config_tensor(cfg: int, nnz: Optional[int] = None) -> SparseTensor:
     """The synthetic tensor of workload `cfg`; `nnz` overrides the count
-    (same dims and distribution) for scaled-down runs."""
+    (same dims and distribution) for scaled-down runs.  With FCOO_SYNTH_CACHE
+    naming a directory, generated tensors are kept there as .npz files and
+    read back on later calls (same arrays; generation is deterministic)."""
+    cache = os.environ.get("FCOO_SYNTH_CACHE")
+    path = None
+    if cache:
+        path = os.path.join(cache, f"synth_cfg{cfg}_{nnz or 'full'}.npz")
+        if os.path.exists(path):
+            d = np.load(path)
+            _note("read", path)
+            return SparseTensor(dims=[int(x) for x in d["dims"]], idx=[d[f"i{m}"] for m in range(len(d["dims"]))],
+                                vals=d["vals"], name=str(d["name"]))
+    t = _make_config_tensor(cfg, nnz)
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        np.savez(path, dims=np.array(t.dims), vals=t.vals, name=np.array(t.name),
+                 **{f"i{m}": t.idx[m] for m in range(len(t.dims))})
+        _note("wrote", path)
+    return t
+
+
+def _make_config_tensor(cfg: int, nnz: Optional[int]) -> SparseTensor:
     c = CONFIGS[cfg]
     z = c["nnz"] if nnz is None else int(nnz)
+    _note("workload", cfg, c["name"], "nnz", z)
     if c.get("planted_rank"):
         base = (zipf_tensor(c["dims"], z, cfg, s=c["skew"], name=c["name"])
                 if c["skew"] else uniform_tensor(c["dims"], z, cfg, name=c["name"]))
