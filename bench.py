@@ -290,7 +290,7 @@ def main():
     ap.add_argument("--ranks", default="16,32")
     ap.add_argument("--nnz", type=int, default=0, help="override the nonzero count (quick runs)")
     ap.add_argument("--threadlen", type=int, default=16)
-    ap.add_argument("--tile", type=int, default=4096)
+    ap.add_argument("--tile", type=int, default=0, help="tile_nnz of every build (0: autotune per op and mode)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
@@ -330,16 +330,24 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     h = Tensor(t.idx, t.vals, t.dims)
+    facs = {R: [torch.tensor(f.astype(np.float32), device=dev)
+                for f in synth.factors(t.dims, R, WORKLOAD_CFG)] for R in Rs}
     t0 = time.time()
     for m in range(t.order):
         for op in ("mttkrp", "ttm"):
-            h.build(m, op, threadlen=args.threadlen, tile_nnz=args.tile)
+            h.build(m, op, threadlen=args.threadlen, tile_nnz=args.tile or 4096)
     build_s = time.time() - t0
     log(f"F-COO built and uploaded (6 builds) in {build_s:.1f}s")
+    tiles = {}
+    if args.tile == 0:
+        # tile size per (op, mode) chosen by timing at the largest rank (not timed below)
+        t0 = time.time()
+        for m in range(t.order):
+            for op in ("mttkrp", "ttm"):
+                r = h.autotune(m, op, facs[max(Rs)], tiles=[2048, 4096, 8192])
+                tiles[f"{op}{m}"] = r["tile_nnz"]
+        log(f"autotuned tile sizes {tiles} in {time.time() - t0:.1f}s")
     infos = {(op, m): h.info(m, op) for m in range(t.order) for op in ("mttkrp", "ttm")}
-
-    facs = {R: [torch.tensor(f.astype(np.float32), device=dev)
-                for f in synth.factors(t.dims, R, WORKLOAD_CFG)] for R in Rs}
     outs = {}
     for R in Rs:
         for m in range(t.order):
@@ -437,7 +445,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{t.name}: SpMTTKRP + SpTTM, every mode, R in {Rs}",
                    "dims": t.dims, "nnz": t.nnz, "ranks": Rs, "threadlen": args.threadlen,
-                   "tile_nnz": args.tile},
+                   "tile_nnz": tiles or args.tile},
         "gflops": round(step_flops / (ms_per_step / 1e3) / 1e9, 1),
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
         "spmttkrp_GBps": {str(R): round(mt[R]["bytes"] / mt[R]["ms"] / 1e6, 1) for R in Rs},

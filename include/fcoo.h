@@ -140,6 +140,27 @@ int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, fl
                 uint8_t *bf, uint32_t *sf, int32_t *seg, int32_t *tile_seg0, int32_t *perm);
 
 /*
+ * fcoo_autotune -- choose the tile size of one built (op, mode) by timing:
+ * each candidate tile_nnz is built (keeping the current threadlen, default
+ * 16) and its operation run once to warm up, then `reps` times between two
+ * HIP events on `stream`; the fastest build is left in place (the paper
+ * tunes its launch shape per dataset, Sec. V, Table V).
+ *   factors  as fcoo_spmttkrp (op = MTTKRP) or factors[mode] = U (op = TTM);
+ *            device data of `dtype`, R columns.
+ *   tiles    host array of `ncand` candidate tile sizes (each a multiple of
+ *            256 and of threadlen), or NULL for {1024, 2048, 4096, 8192, 16384}.
+ *   reps     timed repetitions per candidate (< 1: 3).
+ *   best     host, out (may be NULL): the options of the kept build.
+ *   best_ms  host, out (may be NULL): its mean time per operation (ms).
+ * Allocates a temporary output (rows x R float32) and two events; waits on
+ * `stream` after each candidate.  On error the (op, mode) may be left built
+ * with any candidate or unbuilt.
+ * Errors: as fcoo_build and fcoo_spmttkrp / fcoo_spttm.
+ */
+int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const *factors, int dtype, int R,
+                  const int *tiles, int ncand, int reps, fcoo_opts *best, float *best_ms, void *stream);
+
+/*
  * fcoo_spmttkrp -- M = X_(mode) (Khatri-Rao product of the other factors),
  * computed over the nonzeros in one shot (Eq. 5 / Eq. 6):
  *   M[i, r] = sum over nonzeros e with i_mode(e) = i of

@@ -82,6 +82,8 @@ _SIGS = {
     "fcoo_cp_als_iter": (_i, [_vp, C.POINTER(_vp), _i, _i, _vp, _vp, _i, _vp, _vp, _vp]),
     "fcoo_gram": (_i, [_vp, _i, _vp, _i, _i, _vp, _vp]),
     "fcoo_set_tile_events": (_i, [_vp, _vp, _vp]),
+    "fcoo_autotune": (_i, [_vp, _i, _i, C.POINTER(_vp), _i, _i, _vp, _i, _i, C.POINTER(fcoo_opts),
+                           C.POINTER(C.c_float), _vp]),
     "fcoo_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():

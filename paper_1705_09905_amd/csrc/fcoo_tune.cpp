@@ -1,0 +1,93 @@
+// Per-tensor tuning of the tile size of one (operation, mode): the paper tunes
+// its launch shape per dataset (Sec. V, Table V); here each candidate
+// tile_nnz is built, its operation is timed with HIP events on the caller's
+// stream, and the fastest build is kept.  Host code over the public entry
+// points.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <vector>
+
+#include "fcoo_internal.h"
+
+using namespace fcoo;
+
+namespace {
+
+int run_op(fcoo_tensor *t, int mode, int op, const void *const *factors, int dtype, int R, float *out,
+           void *stream)
+{
+    if (op == FCOO_OP_MTTKRP) return fcoo_spmttkrp(t, mode, factors, dtype, R, out, stream);
+    return fcoo_spttm(t, mode, factors[mode], dtype, R, out, stream);
+}
+
+}  // namespace
+
+extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const *factors, int dtype, int R,
+                             const int *tiles, int ncand, int reps, fcoo_opts *best, float *best_ms,
+                             void *stream)
+{
+    clear_error();
+    if (!t || !factors) return fail(FCOO_EINVAL, "null argument");
+    if (mode < 0 || mode >= t->order) return fail(FCOO_EINVAL, "mode %d out of range", mode);
+    if (op != FCOO_OP_MTTKRP && op != FCOO_OP_TTM) return fail(FCOO_EINVAL, "unknown op %d", op);
+    static const int kDefault[] = {1024, 2048, 4096, 8192, 16384};
+    if (!tiles) {
+        tiles = kDefault;
+        ncand = (int)(sizeof(kDefault) / sizeof(kDefault[0]));
+    }
+    if (ncand < 1) return fail(FCOO_EINVAL, "no candidate tile sizes");
+    if (reps < 1) reps = 3;
+    hipStream_t s = (hipStream_t)stream;
+    int threadlen = 16;
+    fcoo_info_t inf{};
+    if (fcoo_info(t, mode, op, &inf) == FCOO_OK) threadlen = inf.threadlen;
+
+    // output large enough for either operation (TTM: nseg rows, independent of the tile size)
+    fcoo_opts o{threadlen, tiles[0], 0, 0};
+    int rc = fcoo_build(t, mode, op, &o, stream);
+    if (rc) return rc;
+    if ((rc = fcoo_info(t, mode, op, &inf))) return rc;
+    const int64_t rows = op == FCOO_OP_MTTKRP ? t->dims[mode] : inf.nseg;
+    float *out = nullptr;
+    if (rows > 0 && hipMalloc((void **)&out, (size_t)rows * R * sizeof(float)) != hipSuccess)
+        return fail(FCOO_ENOMEM, "autotune output (%lld x %d floats)", (long long)rows, R);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        hipFree(out);
+        return fail(FCOO_EHIP, "hipEventCreate");
+    }
+    float bms = FLT_MAX;
+    int btile = tiles[0];
+    for (int c = 0; c < ncand && rc == FCOO_OK; ++c) {
+        o.tile_nnz = tiles[c];
+        if (c > 0 && (rc = fcoo_build(t, mode, op, &o, stream))) break;
+        if ((rc = run_op(t, mode, op, factors, dtype, R, out, stream))) break;   // warm-up
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(FCOO_EHIP, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && rc == FCOO_OK; ++r) rc = run_op(t, mode, op, factors, dtype, R, out, stream);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(FCOO_EHIP, "timing");
+            break;
+        }
+        ms /= (float)reps;
+        if (ms < bms) {
+            bms = ms;
+            btile = tiles[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(out);
+    if (rc) return rc;
+    if (btile != tiles[ncand - 1]) {
+        o.tile_nnz = btile;
+        if ((rc = fcoo_build(t, mode, op, &o, stream))) return rc;
+    }
+    if (best) *best = o;
+    if (best_ms) *best_ms = bms;
+    return FCOO_OK;
+}

@@ -83,6 +83,25 @@ class Tensor:
         L.check(L.fcoo_build(self._h, int(mode), OPS[op], C.byref(o), stream))
         return self
 
+    def autotune(self, mode: int, op: str, factors, tiles: Optional[Sequence[int]] = None,
+                 reps: int = 3) -> Dict[str, float]:
+        """Time each candidate tile size for (op, mode) with these factors
+        (op 'ttm': factors[mode] is U) and keep the fastest build.  Returns
+        dict(tile_nnz, threadlen, ms)."""
+        if op == "mttkrp":
+            fp, R, dt = self._factors(factors, skip=mode)
+        else:
+            U = factors[mode]
+            ptrs = [0] * self.order
+            ptrs[mode] = U.data_ptr()
+            fp, R, dt = L.ptr_array(ptrs), int(U.shape[1]), _dtype_code(U)
+        cand = None if tiles is None else (C.c_int * len(tiles))(*[int(x) for x in tiles])
+        best = L.fcoo_opts()
+        ms = C.c_float()
+        L.check(L.fcoo_autotune(self._h, int(mode), OPS[op], fp, dt, R, cand, 0 if tiles is None else len(tiles),
+                                int(reps), C.byref(best), C.byref(ms), _stream()))
+        return {"tile_nnz": int(best.tile_nnz), "threadlen": int(best.threadlen), "ms": float(ms.value)}
+
     def info(self, mode: int, op: str = "mttkrp") -> Dict[str, int]:
         i = L.fcoo_info_t()
         L.check(L.fcoo_info(self._h, int(mode), OPS[op], C.byref(i)))

@@ -1,7 +1,8 @@
-"""Parity at the benchmark's full size and launch configuration: the Zipf(1.1)
+"""Parity at the benchmark's full size and launch configurations: the Zipf(1.1)
 100,000 x 80,000 x 60,000 tensor with 20M nonzeros, SpMTTKRP and SpTTM in
-every mode at R = 16 and 32 (threadlen 16, tile 4096), against the float64 C
-oracle computing every output row; plus CP-ALS sweeps (float32 and bfloat16
+every mode at R = 16 and 32 (threadlen 16, each tile size the benchmark's
+autotuner picks from), against the float64 C oracle computing every output
+row; SpTTMc on sampled rows; plus CP-ALS sweeps (float32 and bfloat16
 factors) against the oracle's fits on the same tensor."""
 import numpy as np
 import pytest
@@ -23,29 +24,30 @@ def c2():
 
 
 def test_full_size_spmttkrp_spttm_all_modes(c2):
+    # every tile size the benchmark's autotuner chooses from (2048, 4096, 8192)
     from paper_1705_09905_amd import Tensor
     t = c2
     h = Tensor(t.idx, t.vals, t.dims)
     vals = f32(t.vals)
-    for m in range(3):
-        h.build(m, "mttkrp", threadlen=16, tile_nnz=4096)
-        h.build(m, "ttm", threadlen=16, tile_nnz=4096)
     for R in (16, 32):
         F = [f32(f) for f in synth.factors(t.dims, R, 1)]
         Fd = [to_dev(f) for f in F]
         for m in range(3):
-            tag("full size mttkrp", m, "R", R)
-            M = from_dev(h.spmttkrp(m, Fd))
-            err = rel_fro(M, cpu.mttkrp(t.dims, t.idx, vals, F, m))
-            tag("rel err", err)
-            assert err <= TOL_F32
-            tag("full size ttm", m, "R", R)
-            fib, Y = cpu.ttm(t.dims, t.idx, vals, F[m], m)
-            Yd = from_dev(h.spttm(m, Fd[m]))
-            assert Yd.shape == Y.shape
-            err = rel_fro(Yd, Y)
-            tag("rel err", err)
-            assert err <= TOL_F32
+            expM = cpu.mttkrp(t.dims, t.idx, vals, F, m)
+            fib, expY = cpu.ttm(t.dims, t.idx, vals, F[m], m)
+            for T in (2048, 4096, 8192):
+                tag("full size mttkrp", m, "R", R, "tile", T)
+                h.build(m, "mttkrp", threadlen=16, tile_nnz=T)
+                err = rel_fro(from_dev(h.spmttkrp(m, Fd)), expM)
+                tag("rel err", err)
+                assert err <= TOL_F32
+                tag("full size ttm", m, "R", R, "tile", T)
+                h.build(m, "ttm", threadlen=16, tile_nnz=T)
+                Yd = from_dev(h.spttm(m, Fd[m]))
+                assert Yd.shape == expY.shape
+                err = rel_fro(Yd, expY)
+                tag("rel err", err)
+                assert err <= TOL_F32
 
 
 def test_full_size_cp_als_f32_and_bf16(c2):

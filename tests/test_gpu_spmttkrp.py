@@ -187,3 +187,23 @@ def test_spmttkrp_values_is_adjoint_with_replaced_values():
                                        [to_dev(f) for f in F]))
         exp = cpu.mttkrp(t.dims, t.idx, f32(g), [f32(f) for f in F], mode)
         assert rel_fro(M, exp) <= TOL_F32
+
+
+def test_autotune_keeps_fastest_build_and_stays_correct():
+    Tensor = _fcoo()
+    t = synth.zipf_tensor([3000, 2000, 1000], 200000, cfg=31)
+    F = synth.small_factors(t.dims, 16, seed=1)
+    Fd = [to_dev(f) for f in F]
+    h = Tensor(t.idx, t.vals, t.dims)
+    tag("autotune mttkrp mode 1")
+    r = h.autotune(1, "mttkrp", Fd, tiles=[512, 2048, 8192])
+    assert r["tile_nnz"] in (512, 2048, 8192) and r["ms"] > 0
+    assert h.info(1)["tile_nnz"] == r["tile_nnz"]
+    M = from_dev(h.spmttkrp(1, Fd))
+    assert rel_fro(M, cpu.mttkrp(t.dims, t.idx, f32(t.vals), [f32(f) for f in F], 1)) <= TOL_F32
+    tag("autotune ttm mode 2")
+    r = h.autotune(2, "ttm", Fd)
+    assert r["tile_nnz"] in (1024, 2048, 4096, 8192, 16384)
+    assert h.info(2, "ttm")["tile_nnz"] == r["tile_nnz"]
+    _, Y = cpu.ttm(t.dims, t.idx, f32(t.vals), f32(F[2]), 2)
+    assert rel_fro(from_dev(h.spttm(2, Fd[2])), Y) <= TOL_F32
