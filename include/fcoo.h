@@ -67,7 +67,11 @@ typedef struct {
                         threadlen (default 4096). */
     int host_only;   /* 1: build the host arrays only (no device upload), e.g. to
                         fcoo_export them on a machine without a GPU. */
-    int reserved;
+    int device;      /* 1: sort and encode on the GPU (same arrays, bit for bit);
+                        needs the packed sort key within 64 bits, 0 < Z < 2^31,
+                        and holds about 32 bytes per nonzero of scratch while it
+                        runs.  The per-nonzero arrays then live on the device only
+                        (fcoo_export copies them back).  Exclusive with host_only. */
 } fcoo_opts;
 
 /* Sizes of one built (op, mode). */

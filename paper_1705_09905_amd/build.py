@@ -27,6 +27,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = [
     "fcoo_host.cpp",
     "fcoo_tune.cpp",
+    "fcoo_devbuild.hip",
     "fcoo_ops.hip",
     "fcoo_cp.hip",
     "seg_f32.hip",

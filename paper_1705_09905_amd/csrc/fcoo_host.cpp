@@ -121,9 +121,7 @@ static int bit_width(int64_t d)  // bits to hold 0..d-1
 
 int64_t Built::format_bytes() const
 {
-    int64_t s = 0;
-    for (auto &p : pidx) s += (int64_t)p.size() * 4;
-    return s + (int64_t)val.size() * 4 + (int64_t)bf.size() + (int64_t)sf.size() * 4;
+    return 4 * nnz * (int64_t)pmodes.size() + 4 * nnz + (nnz + 7) / 8 + 4 * ((npart + 31) / 32);
 }
 
 void Built::free_device()
@@ -188,6 +186,11 @@ static int upload(T **dst, const T *src, int64_t n, int64_t pad_elems, hipStream
     if (n) FCOO_HIP(hipMemcpyAsync(*dst, src, (size_t)n * sizeof(T), hipMemcpyHostToDevice, s));
     *acct += (int64_t)bytes;
     return FCOO_OK;
+}
+
+int upload_i32(int32_t **dst, const std::vector<int32_t> &v, int64_t pad, hipStream_t s, int64_t *acct)
+{
+    return upload(dst, v.data(), (int64_t)v.size(), pad, s, acct);
 }
 
 int upload_coo(fcoo_tensor *t, hipStream_t s)
@@ -275,7 +278,7 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
             for (size_t q = 0; q < b.pmodes.size(); ++q) b.pidx[q][s] = t->idx[b.pmodes[q]][e];
             bool h = (s == 0);
             if (!h) {
-                if (packed) h = (key[s] >> pbits) != (key[s - 1] >> pbits);
+                if (packed) h = pbits < 64 && (key[s] >> pbits) != (key[s - 1] >> pbits);
                 else
                     for (int m : b.imodes)
                         if (t->idx[m][e] != t->idx[m][perm[s - 1]]) { h = true; break; }
@@ -350,6 +353,37 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
     }
     b.built = true;
     return FCOO_OK;
+}
+
+void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::vector<int64_t> &hb)
+{
+    const int64_t ntiles = b.ntiles, cnt = b.nseg;
+    auto out_row = [&](int64_t g) -> int32_t {
+        return op == FCOO_OP_MTTKRP ? b.seg[(size_t)g] : (int32_t)g;
+    };
+    b.fix.clear();
+    int64_t last = -1;
+    for (int64_t tb = 0; tb < ntiles; ++tb) {
+        if (hb[tb + 1] == hb[tb]) continue;          // no head in tile tb
+        if (tb >= 1) {
+            b.fix.push_back((int32_t)tb);
+            b.fix.push_back((int32_t)last);
+            b.fix.push_back(out_row(hb[tb] - 1));
+        }
+        last = tb;
+    }
+    if (b.nnz > 0) {
+        b.fix.push_back((int32_t)ntiles);
+        b.fix.push_back((int32_t)last);
+        b.fix.push_back(out_row(cnt - 1));
+    }
+    b.empty_rows.clear();
+    if (op == FCOO_OP_MTTKRP) {
+        std::vector<uint8_t> present(t->dims[mode], 0);
+        for (int64_t g = 0; g < cnt; ++g) present[b.seg[g]] = 1;
+        for (int64_t i = 0; i < t->dims[mode]; ++i)
+            if (!present[i]) b.empty_rows.push_back((int32_t)i);
+    }
 }
 
 static int build_device(Built &b, hipStream_t s)
@@ -467,6 +501,8 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     int threadlen = opts && opts->threadlen ? opts->threadlen : 16;
     int tile_nnz = opts && opts->tile_nnz ? opts->tile_nnz : 4096;
     const bool host_only = opts && opts->host_only;
+    const bool on_gpu = opts && opts->device;
+    if (host_only && on_gpu) return fail(FCOO_EINVAL, "host_only and device are exclusive");
     if (threadlen != 8 && threadlen != 16 && threadlen != 32 && threadlen != 64)
         return fail(FCOO_EINVAL, "threadlen %d not in {8, 16, 32, 64}", threadlen);
     if (tile_nnz <= 0 || tile_nnz % 256 || tile_nnz % threadlen || tile_nnz > (1 << 20))
@@ -475,6 +511,18 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     Built &b = t->b[op][mode];
     b.free_device();
     int rc;
+    if (on_gpu) {
+        try {
+            rc = build_on_device(t, b, mode, op, threadlen, tile_nnz, (hipStream_t)stream);
+        } catch (const std::bad_alloc &) {
+            rc = fail(FCOO_ENOMEM, "device build (host side)");
+        }
+        if (rc) {
+            b.free_device();
+            b = Built();
+        }
+        return rc;
+    }
     try {
         rc = build_host(t, b, mode, op, threadlen, tile_nnz);
     } catch (const std::bad_alloc &) {
@@ -515,6 +563,20 @@ int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, fl
     clear_error();
     const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false);
     if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    if (!b->host_arrays) {
+        // built on the GPU: the per-nonzero arrays live on the device only
+        const int64_t Z = b->nnz;
+        if (pidx)
+            for (size_t q = 0; q < b->pmodes.size(); ++q)
+                if (pidx[q]) FCOO_HIP(hipMemcpy(pidx[q], b->d_pidx[q], (size_t)Z * 4, hipMemcpyDeviceToHost));
+        if (val) FCOO_HIP(hipMemcpy(val, b->d_val, (size_t)Z * 4, hipMemcpyDeviceToHost));
+        if (bf) FCOO_HIP(hipMemcpy(bf, b->d_bf, (size_t)(Z + 7) / 8, hipMemcpyDeviceToHost));
+        if (sf) FCOO_HIP(hipMemcpy(sf, b->d_sf, (size_t)((b->npart + 31) / 32) * 4, hipMemcpyDeviceToHost));
+        if (perm) FCOO_HIP(hipMemcpy(perm, b->d_perm, (size_t)Z * 4, hipMemcpyDeviceToHost));
+        if (seg) memcpy(seg, b->seg.data(), b->seg.size() * 4);
+        if (tile_seg0) memcpy(tile_seg0, b->tile_seg0.data(), b->tile_seg0.size() * 4);
+        return FCOO_OK;
+    }
     if (pidx)
         for (size_t q = 0; q < b->pidx.size(); ++q)
             if (pidx[q]) memcpy(pidx[q], b->pidx[q].data(), b->pidx[q].size() * 4);

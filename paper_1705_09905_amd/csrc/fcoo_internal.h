@@ -31,6 +31,7 @@ void clear_error();
 struct Built {
     bool built = false;
     bool on_device = false;
+    bool host_arrays = true;                  // false: built on the GPU, per-nonzero arrays on the device only
     int op = 0, mode = 0, threadlen = 0, tile_nnz = 0;
     int64_t nnz = 0, nseg = 0, npart = 0, ntiles = 0;
     std::vector<int> imodes, pmodes;
@@ -112,6 +113,12 @@ namespace fcoo {
 int ensure_device_floats(float **p, int64_t *cap, int64_t need, hipStream_t s);
 int ensure_device_doubles(double **p, int64_t *cap, int64_t need, hipStream_t s);
 int upload_coo(fcoo_tensor *t, hipStream_t s);
+int upload_i32(int32_t **dst, const std::vector<int32_t> &v, int64_t pad, hipStream_t s, int64_t *acct);
+// carry fix-up chains and empty output rows from the per-tile head counts
+// (heads_before[t] = heads before nonzero t * tile_nnz, t = 0 .. ntiles) and b.seg
+void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::vector<int64_t> &heads_before);
+// the F-COO build of one (op, mode) on the GPU (same arrays as the host build)
+int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, hipStream_t s);
 int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
 
 // launchers implemented in the .hip files (return FCOO_OK or an error code)

@@ -77,8 +77,9 @@ class Tensor:
 
     # ---- build / inspect --------------------------------------------------
     def build(self, mode: int, op: str = "mttkrp", threadlen: int = 0, tile_nnz: int = 0,
-              host_only: bool = False) -> "Tensor":
-        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 0)
+              host_only: bool = False, device: bool = False) -> "Tensor":
+        """F-COO encoding of (op, mode); device=True sorts and encodes on the GPU."""
+        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0)
         stream = C.c_void_p(0) if host_only else _stream()
         L.check(L.fcoo_build(self._h, int(mode), OPS[op], C.byref(o), stream))
         return self
