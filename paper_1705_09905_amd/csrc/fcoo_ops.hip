@@ -24,7 +24,15 @@ __global__ __launch_bounds__(256) void fixup_kernel(const int32_t *__restrict__ 
         // wide rows (SpTTMc): one column per thread, the chain summed in order
         for (int c = tid; c < R; c += 256) {
             float v = cb[(int64_t)ta * R + c];
-            for (int64_t t = (int64_t)ta + 1; t < tb; ++t) v += ca[t * R + c];
+            int64_t t = (int64_t)ta + 1;
+            for (; t + 7 < tb; t += 8) {
+                float x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = ca[(t + u) * R + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v += x[u];
+            }
+            for (; t < tb; ++t) v += ca[t * R + c];
             if (tb < ntiles) v += ca[(int64_t)tb * R + c];
             out[(int64_t)row * R + c] = v;
         }
@@ -33,8 +41,19 @@ __global__ __launch_bounds__(256) void fixup_kernel(const int32_t *__restrict__ 
     const int slots = 256 / R;
     const int slot = tid / R, c = tid - (tid / R) * R;
     float s = 0.f;
-    if (slot < slots)
-        for (int64_t t = (int64_t)ta + 1 + slot; t < tb; t += slots) s += ca[t * R + c];
+    if (slot < slots) {
+        // long chains (a slice over hundreds of tiles): 8 loads in flight,
+        // then the adds in tile order
+        int64_t t = (int64_t)ta + 1 + slot;
+        for (; t + 7 * slots < tb; t += 8 * slots) {
+            float x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = ca[(t + u * slots) * R + c];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += x[u];
+        }
+        for (; t < tb; t += slots) s += ca[t * R + c];
+    }
     red[tid] = s;
     __syncthreads();
     if (tid < R) {
