@@ -116,6 +116,7 @@ template <> struct Raw<float, 4> { float4 v; };
 template <> struct Raw<bf16raw, 8> { uint4 v; };
 template <> struct Raw<float, 1> { float v; };
 template <> struct Raw<bf16raw, 1> { uint32_t v; };
+template <> struct Raw<bf16raw, 2> { uint32_t v; };   // two consecutive bfloat16
 
 template <typename FT, int VW>
 __device__ __forceinline__ void load_raw(const FT *__restrict__ p, Raw<FT, VW> &r)
@@ -123,6 +124,7 @@ __device__ __forceinline__ void load_raw(const FT *__restrict__ p, Raw<FT, VW> &
     if constexpr (sizeof(FT) == 4 && VW == 4) r.v = *reinterpret_cast<const float4 *>(p);
     else if constexpr (sizeof(FT) == 2 && VW == 8) r.v = *reinterpret_cast<const uint4 *>(p);
     else if constexpr (sizeof(FT) == 4 && VW == 1) r.v = *reinterpret_cast<const float *>(p);
+    else if constexpr (sizeof(FT) == 2 && VW == 2) r.v = *reinterpret_cast<const uint32_t *>(p);
     else r.v = (uint32_t)(*reinterpret_cast<const uint16_t *>(p));
 }
 
@@ -132,6 +134,7 @@ __device__ __forceinline__ void set_one(Raw<FT, VW> &r)
     if constexpr (sizeof(FT) == 4 && VW == 4) r.v = make_float4(1.f, 1.f, 1.f, 1.f);
     else if constexpr (sizeof(FT) == 2 && VW == 8) r.v = make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u);
     else if constexpr (sizeof(FT) == 4 && VW == 1) r.v = 1.f;
+    else if constexpr (sizeof(FT) == 2 && VW == 2) r.v = 0x3F803F80u;
     else r.v = 0x3F80u;
 }
 
@@ -147,6 +150,9 @@ __device__ __forceinline__ void to_float(const Raw<FT, VW> &r, float (&out)[VW])
         out[6] = bf16_to_f32(r.v.w & 0xFFFFu); out[7] = bf16_to_f32(r.v.w >> 16);
     } else if constexpr (sizeof(FT) == 4 && VW == 1) {
         out[0] = r.v;
+    } else if constexpr (sizeof(FT) == 2 && VW == 2) {
+        out[0] = bf16_to_f32(r.v & 0xFFFFu);
+        out[1] = bf16_to_f32(r.v >> 16);
     } else {
         out[0] = bf16_to_f32(r.v);
     }

@@ -199,7 +199,12 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         // a lane's VW columns must lie in one row piece of the (last) factor
         L.vec = ((p.kron ? p.kr[np - 1] : R) % V) == 0;
         const int VW = L.vec ? V : 1;
-        int lpn = next_pow2((R + VW - 1) / VW);
+        // SpTTMc: KB columns of the second-to-last mode per lane when they divide it
+        const int KBv = p.dtype == FCOO_F32 ? 4 : 2;
+        L.kb = (p.kron && L.vec && np >= 2 && p.kr[np - 2] % KBv == 0) ? KBv : 1;
+        const int AW = VW * L.kb;
+        const int lanes = (R + AW - 1) / AW;          // lanes per nonzero over the whole row
+        int lpn = next_pow2(lanes);
         if (p.kron) {
             for (int q = 0; q < np; ++q) a.kr[q] = p.kr[q];
             if (lpn < 4) lpn = 4;
@@ -209,8 +214,8 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         }
         if (!L.vec) lpn = 64;
         L.lpn = lpn;
-        const int rt = lpn * VW;
-        const int nrt = (R + rt - 1) / rt;
+        const int rt = lpn * AW;
+        const int nrt = (lanes + lpn - 1) / lpn;
         if (resid && nrt > 1)
             return fail(FCOO_EUNSUPPORTED, "fused residual needs R <= %d for this dtype (R = %d)", rt, R);
         L.npt = np <= 3 ? np : 0;

@@ -14,6 +14,7 @@ struct SegLaunch {
     int lpn;         // lanes per nonzero: 1, 2, 4, 8, 16 (vector; SpTTMc up to 64) or 64 (scalar)
     int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
     bool rowmap;     // output row = seg_row[segment] (SpMTTKRP) or the segment ordinal (SpTTM)
+    int kb;          // SpTTMc: column blocks per lane (1, or KronBlock<FT>::KB)
     dim3 grid;
 };
 
@@ -25,10 +26,10 @@ static hipError_t seg_go(const SegLaunch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename FT, int VW, int LPN, int NP>
+template <typename FT, int VW, int LPN, int NP, int KB = 1>
 static hipError_t seg_go_k(const SegLaunch &L, hipStream_t s)
 {
-    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, false, true, true>), L.grid, dim3(256), 0, s,
+    hipLaunchKernelGGL((dev::seg_tile_kernel<FT, VW, LPN, NP, false, true, true, KB>), L.grid, dim3(256), 0, s,
                        L.args);
     return hipGetLastError();
 }
@@ -70,28 +71,39 @@ static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
 // SpTTMc: Kronecker rows (generic path), output row = seg_row[segment].
 // Lanes per nonzero: 4 .. 64 (vector) or 64 (scalar); product modes 2, 3 or
 // a runtime count.
-template <typename FT, int VW, int LPN>
+template <typename FT, int VW, int LPN, int KB>
 static hipError_t seg_np_kron(const SegLaunch &L, hipStream_t s)
 {
     switch (L.npt) {
-        case 2: return seg_go_k<FT, VW, LPN, 2>(L, s);
-        case 3: return seg_go_k<FT, VW, LPN, 3>(L, s);
-        default: return seg_go_k<FT, VW, LPN, 0>(L, s);
+        case 2: return seg_go_k<FT, VW, LPN, 2, KB>(L, s);
+        case 3: return seg_go_k<FT, VW, LPN, 3, KB>(L, s);
+        default: return seg_go_k<FT, VW, LPN, 0, KB>(L, s);
+    }
+}
+
+// column blocks per lane with SpTTMc: 4 (float32) / 2 (bfloat16) elements of
+// the second-to-last product mode, or 1
+template <typename FT> struct KronBlock { static constexpr int KB = sizeof(FT) == 4 ? 4 : 2; };
+
+template <typename FT, int KB>
+static hipError_t seg_lpn_kron(const SegLaunch &L, hipStream_t s)
+{
+    constexpr int V = dev::Elem<FT>::VEC;
+    switch (L.lpn) {
+        case 4: return seg_np_kron<FT, V, 4, KB>(L, s);
+        case 8: return seg_np_kron<FT, V, 8, KB>(L, s);
+        case 16: return seg_np_kron<FT, V, 16, KB>(L, s);
+        case 32: return seg_np_kron<FT, V, 32, KB>(L, s);
+        default: return seg_np_kron<FT, V, 64, KB>(L, s);
     }
 }
 
 template <typename FT>
 static hipError_t seg_dispatch_kron(const SegLaunch &L, hipStream_t s)
 {
-    constexpr int V = dev::Elem<FT>::VEC;
     if (!L.vec) return seg_go_k<FT, 1, 64, 0>(L, s);
-    switch (L.lpn) {
-        case 4: return seg_np_kron<FT, V, 4>(L, s);
-        case 8: return seg_np_kron<FT, V, 8>(L, s);
-        case 16: return seg_np_kron<FT, V, 16>(L, s);
-        case 32: return seg_np_kron<FT, V, 32>(L, s);
-        default: return seg_np_kron<FT, V, 64>(L, s);
-    }
+    if (L.kb > 1) return seg_lpn_kron<FT, KronBlock<FT>::KB>(L, s);
+    return seg_lpn_kron<FT, 1>(L, s);
 }
 
 hipError_t seg_launch_f32(const SegLaunch &L, hipStream_t s);

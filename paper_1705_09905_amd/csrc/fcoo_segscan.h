@@ -246,7 +246,7 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
     out.v = take_a ? a.v : b.v;
 }
 
-template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false>
+template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>
 __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
@@ -257,7 +257,11 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     constexpr int CL = CH0 > LPN ? CH0 : LPN;         // steps per chunk (stream granule)
     constexpr int CH = CH0 < CL ? CH0 : CL;           // steps per gather batch
     constexpr int U = CL / LPN;                       // stream entries per lane per chunk
-    constexpr int RT = LPN * VW;                      // columns of this rank tile
+    // KRON with KB > 1: a lane owns KB blocks of VW columns, one per element of
+    // a KB-wide piece of the second-to-last product mode's row
+    static_assert(KB == 1 || (KRON && !RESID), "column blocks are for SpTTMc");
+    constexpr int AW = VW * KB;                       // accumulated columns per lane
+    constexpr int RT = LPN * AW;                      // columns of this rank tile
 
     __shared__ int s_f[4];
     __shared__ float s_a[4][RT];
@@ -275,16 +279,30 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     const int64_t wstart = t0 + (int64_t)w * Q * S;
     const int64_t rs = wstart + (int64_t)q * S;
     const int64_t re = rs + S < A.nnz ? rs + S : A.nnz;
-    const int col = (int)blockIdx.y * RT + j * VW;
-    const bool cval = col < A.R;
-    const int colc = cval ? col : 0;                  // lanes past R read column 0, never store
-    const int R = A.R;
     const int np = NP > 0 ? NP : A.np;
+    int col, colc;
+    bool cval;
+    if constexpr (KB == 1) {
+        col = (int)blockIdx.y * RT + j * VW;
+        cval = col < A.R;
+        colc = cval ? col : 0;                        // lanes past R read column 0, never store
+    } else {
+        // lane gl: block gl % nb2 of the last mode, block (gl / nb2) % nb1 of
+        // the one before, then the earlier modes' combined index
+        const int gl = (int)blockIdx.y * LPN + j;
+        const int nb2 = A.kr[np - 1] / VW, nb1 = A.kr[np - 2] / KB;
+        cval = gl < A.R / AW;
+        const int g2 = cval ? gl : 0;
+        col = ((g2 / (nb2 * nb1)) * A.kr[np - 2] + ((g2 / nb2) % nb1) * KB) * A.kr[np - 1] + (g2 % nb2) * VW;
+        colc = col;
+    }
+    const int R = A.R;
     const uint64_t R4 = (uint64_t)R * sizeof(FT);
     const char *fb[NPM];
     uint64_t R4k[NPM];                                // KRON: row bytes of each product mode
     if constexpr (KRON) {
-        // digits of this lane's first column, last product mode fastest
+        // digits of this lane's first column, last product mode fastest (with
+        // column blocks, the second-to-last digit starts this lane's KB-piece)
         int rem = colc;
 #pragma unroll
         for (int qq = NPM - 1; qq >= 0; --qq) {
@@ -305,6 +323,22 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
             R4k[qq] = R4;
         }
     }
+
+    // store the lane's AW columns of one output (or carry) row
+    const int kstride = KB > 1 ? A.kr[np - 1] : 0;   // column distance between a lane's blocks
+    auto store_acc = [&](float *rowp, const float (&v)[AW]) {
+        if constexpr (KB == 1) {
+            store_row<VW>(rowp + col, v);
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                float tv[VW];
+#pragma unroll
+                for (int k = 0; k < VW; ++k) tv[k] = v[kb * VW + k];
+                store_row<VW>(rowp + col + kb * kstride, tv);
+            }
+        }
+    };
 
     // first chunk of the stream and the tile's segment ordinal: issued first
     // fast path: 16-byte stream vectors in super-chunks; generic path: chunks
@@ -355,7 +389,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 
     // ---- 2. walk the run, one chunk at a time: gather this chunk's rows,
     //         then put the next chunk's stream in flight, then reduce
-    float acc[VW], pre[VW];
+    float acc[AW], pre[AW];
     zero(acc);
     zero(pre);
     int have = 0;
@@ -372,15 +406,15 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     }
 
     // one step of the general path (a head may occur, the chunk may be short)
-    auto step = [&](const float (&h)[VW], float v, uint64_t hm, int st, int n) {
+    auto on_head = [&](uint64_t hm, int st) {
         if ((hm >> st) & 1ull) {
             if (have && cval) {
                 const int64_t row = ROWMAP ? (int64_t)currow : (int64_t)g;
-                store_row<VW>(A.out + row * R + col, acc);
+                store_acc(A.out + row * R, acc);
             }
             if (!have) {
 #pragma unroll
-                for (int k = 0; k < VW; ++k) pre[k] = acc[k];
+                for (int k = 0; k < AW; ++k) pre[k] = acc[k];
             }
             have = 1;
             zero(acc);
@@ -389,6 +423,9 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
             if constexpr (RESID)
                 load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)currow * R + colc, own);
         }
+    };
+    auto step = [&](const float (&h)[AW], float v, uint64_t hm, int st, int n) {
+        on_head(hm, st);
         if (st < n) {
             if constexpr (RESID) {
                 // lanes past R hold column 0 (clamped reads): kept out of the dot product
@@ -403,7 +440,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
                 if (j == 0) lsum += r * r;
             } else {
 #pragma unroll
-                for (int k = 0; k < VW; ++k) acc[k] += v * h[k];
+                for (int k = 0; k < AW; ++k) acc[k] += v * h[k];
             }
         }
     };
@@ -499,13 +536,18 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
                 constexpr int S0 = decltype(sbc)::value * CH;
                 Raw<FT, VW> rows[CH][NPM];
                 Raw<FT, 1> ks[CH][NPM];                 // KRON: one element of each non-last mode
+                Raw<FT, KB> kp[CH];                     // KRON, KB > 1: KB elements of the second-to-last mode
                 static_for<CH>([&](auto jjc) {
                     constexpr int ST = S0 + decltype(jjc)::value;
 #pragma unroll
                     for (int qq = 0; qq < NPM; ++qq) {
                         const int idx = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
                         const FT *p = reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * R4k[qq]);
-                        if constexpr (KRON) {
+                        if constexpr (KRON && KB > 1) {
+                            if (qq < np - 2) load_raw<FT, 1>(p, ks[ST - S0][qq]);
+                            else if (qq == np - 2) load_raw<FT, KB>(p, kp[ST - S0]);
+                            else if (qq == np - 1) load_raw<FT, VW>(p, rows[ST - S0][0]);
+                        } else if constexpr (KRON) {
                             if (qq < np - 1) load_raw<FT, 1>(p, ks[ST - S0][qq]);
                             else if (qq == np - 1) load_raw<FT, VW>(p, rows[ST - S0][0]);
                         } else {
@@ -517,8 +559,36 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
                 static_for<CH>([&](auto jjc) {
                     constexpr int ST = S0 + decltype(jjc)::value;
                     const float v = bcast_imm_f<LPN, ST % LPN>(cur.v[ST / LPN]);
-                    float h[VW];
-                    to_float<FT, VW>(rows[ST - S0][0], h);
+                    float h[AW];
+                    if constexpr (KRON && KB > 1) {
+                        (void)h;
+                        float u2[VW], u1[KB];
+                        to_float<FT, VW>(rows[ST - S0][0], u2);
+                        to_float<FT, KB>(kp[ST - S0], u1);
+                        float m = 1.f;
+#pragma unroll
+                        for (int qq = 0; qq < NPM - 2; ++qq) {
+                            if (qq < np - 2) {
+                                float x[1];
+                                to_float<FT, 1>(ks[ST - S0][qq], x);
+                                m *= x[0];
+                            }
+                        }
+                        // column (kb, k) gains (v m u1[kb]) u2[k]: one multiply-add per column
+                        on_head(hm, ST);
+                        if (ST < n) {
+                            const float vm = v * m;
+#pragma unroll
+                            for (int kb = 0; kb < KB; ++kb) {
+                                const float c1 = vm * u1[kb];
+#pragma unroll
+                                for (int k = 0; k < VW; ++k) acc[kb * VW + k] += c1 * u2[k];
+                            }
+                        }
+                        return;
+                    } else {
+                        to_float<FT, VW>(rows[ST - S0][0], h);
+                    }
                     if constexpr (KRON) {
                         float m = 1.f;
 #pragma unroll
@@ -549,35 +619,35 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
 
     // ---- 3. wave-level segmented scan of the runs' (f, a, b)
     const int fo = have;
-    float ao[VW];
+    float ao[AW];
     int f = have;
-    float a[VW], b[VW];
+    float a[AW], b[AW];
 #pragma unroll
-    for (int k = 0; k < VW; ++k) {
+    for (int k = 0; k < AW; ++k) {
         ao[k] = have ? pre[k] : acc[k];
         a[k] = ao[k];
         b[k] = acc[k];
     }
-    wave_segscan<LPN, VW>(f, a, b, q);
+    wave_segscan<LPN, AW>(f, a, b, q);
     {   // exclusive prefix of this group: the inclusive value of group q - 1
         const int fp = __shfl_up(f, LPN, 64);
-        float bp[VW];
+        float bp[AW];
 #pragma unroll
-        for (int k = 0; k < VW; ++k) bp[k] = __shfl_up(b[k], LPN, 64);
+        for (int k = 0; k < AW; ++k) bp[k] = __shfl_up(b[k], LPN, 64);
         if (q >= 1 && fo && fp && cval) {
-            float v[VW];
+            float v[AW];
 #pragma unroll
-            for (int k = 0; k < VW; ++k) v[k] = bp[k] + ao[k];
+            for (int k = 0; k < AW; ++k) v[k] = bp[k] + ao[k];
             const int gc = H_run - 1;
             const int64_t row = ROWMAP ? (int64_t)A.seg_row[gc] : (int64_t)gc;
-            store_row<VW>(A.out + row * R + col, v);
+            store_acc(A.out + row * R, v);
         }
     }
     if (q == Q - 1) {
 #pragma unroll
-        for (int k = 0; k < VW; ++k) {
-            s_a[w][j * VW + k] = a[k];
-            s_b[w][j * VW + k] = b[k];
+        for (int k = 0; k < AW; ++k) {
+            s_a[w][j * AW + k] = a[k];
+            s_b[w][j * AW + k] = b[k];
         }
         if (j == 0) s_f[w] = f;
     }
@@ -594,32 +664,32 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     //         earlier wave of the tile; then the tile's carries
     if (q == 0 && w >= 1 && s_f[w] && cval) {
         int fx = s_f[0];
-        float bx[VW];
+        float bx[AW];
 #pragma unroll
-        for (int k = 0; k < VW; ++k) bx[k] = s_b[0][j * VW + k];
+        for (int k = 0; k < AW; ++k) bx[k] = s_b[0][j * AW + k];
         for (int i = 1; i < w; ++i) {
 #pragma unroll
-            for (int k = 0; k < VW; ++k) bx[k] = s_f[i] ? s_b[i][j * VW + k] : bx[k] + s_a[i][j * VW + k];
+            for (int k = 0; k < AW; ++k) bx[k] = s_f[i] ? s_b[i][j * AW + k] : bx[k] + s_a[i][j * AW + k];
             fx |= s_f[i];
         }
         if (fx) {
-            float v[VW];
+            float v[AW];
 #pragma unroll
-            for (int k = 0; k < VW; ++k) v[k] = bx[k] + s_a[w][j * VW + k];
+            for (int k = 0; k < AW; ++k) v[k] = bx[k] + s_a[w][j * AW + k];
             const int gc = s_hw[w] - 1;
             const int64_t row = ROWMAP ? (int64_t)A.seg_row[gc] : (int64_t)gc;
-            store_row<VW>(A.out + row * R + col, v);
+            store_acc(A.out + row * R, v);
         }
     }
     if (w == 0 && q == 0 && cval) {
         int ft = s_f[0];
-        float at[VW], bt[VW];
+        float at[AW], bt[AW];
 #pragma unroll
-        for (int k = 0; k < VW; ++k) { at[k] = s_a[0][j * VW + k]; bt[k] = s_b[0][j * VW + k]; }
+        for (int k = 0; k < AW; ++k) { at[k] = s_a[0][j * AW + k]; bt[k] = s_b[0][j * AW + k]; }
         for (int i = 1; i < 4; ++i) {
 #pragma unroll
-            for (int k = 0; k < VW; ++k) {
-                const float ai = s_a[i][j * VW + k], bi = s_b[i][j * VW + k];
+            for (int k = 0; k < AW; ++k) {
+                const float ai = s_a[i][j * AW + k], bi = s_b[i][j * AW + k];
                 const float na = ft ? at[k] : at[k] + ai;
                 const float nb = s_f[i] ? bi : bt[k] + ai;
                 at[k] = na;
@@ -627,8 +697,8 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
             }
             ft |= s_f[i];
         }
-        store_row<VW>(A.carry_a + tile * R + col, at);
-        store_row<VW>(A.carry_b + tile * R + col, bt);
+        store_acc(A.carry_a + tile * R, at);
+        store_acc(A.carry_b + tile * R, bt);
     }
     if constexpr (RESID) {
         if (tid == 0 && blockIdx.y == 0 && A.partial)

@@ -2,7 +2,9 @@
 oracle, through the C ABI: Kronecker rows of the product modes summed per
 slice of the SpMTTKRP encoding.  Factors may differ in column count; the
 vector path needs the last product mode's count to be a multiple of the
-vector width (4 float32 / 8 bfloat16), the scalar path takes any."""
+vector width (4 float32 / 8 bfloat16), the scalar path takes any; with the
+second-to-last count a multiple of 4 (float32) / 2 (bfloat16) a lane also
+owns that many column blocks.  The rank shapes below cover all three."""
 import numpy as np
 import pytest
 
@@ -77,7 +79,8 @@ def test_invariant_to_threadlen_and_tile(L, T):
 
 
 @pytest.mark.parametrize("dims,ranks", [([8, 7, 6, 5], [4, 4, 4, 4]), ([6, 5, 4, 3, 3], [2, 3, 2, 4, 4]),
-                                        ([50, 40], [8, 12]), ([9, 8, 7, 6], [3, 2, 5, 3])])
+                                        ([50, 40], [8, 12]), ([9, 8, 7, 6], [3, 2, 5, 3]),
+                                        ([6, 5, 4, 3, 3], [4, 4, 4, 4, 4]), ([7, 6, 5, 4], [8, 2, 8, 8])])
 def test_orders_2_to_5(dims, ranks):
     t = synth.random_small(dims, 1500, seed=len(dims))
     for mode in range(len(dims)):
