@@ -161,7 +161,7 @@ int grid_of(int64_t n, int cap = 65535 * 16)
 // device temporaries of one build, freed on every exit path
 struct Scratch {
     std::vector<void *> p;
-    ~Scratch() { for (void *x : p) hipFree(x); }
+    ~Scratch() { for (void *x : p) (void)hipFree(x); }
     template <typename T>
     int get(T **out, int64_t n)
     {

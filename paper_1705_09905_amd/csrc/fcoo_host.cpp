@@ -126,10 +126,10 @@ int64_t Built::format_bytes() const
 
 void Built::free_device()
 {
-    for (auto &p : d_pidx) { if (p) hipFree(p); p = nullptr; }
+    for (auto &p : d_pidx) { if (p) (void)hipFree(p); p = nullptr; }
     void *ptrs[] = {d_val, d_bf, d_sf, d_seg_row, d_tile_seg0, d_perm, d_fix, d_empty, d_carry,
                     d_gperm, d_partial};
-    for (void *p : ptrs) if (p) hipFree(p);
+    for (void *p : ptrs) if (p) (void)hipFree(p);
     d_val = nullptr; d_bf = nullptr; d_sf = nullptr; d_seg_row = nullptr; d_tile_seg0 = nullptr;
     d_perm = nullptr; d_fix = nullptr; d_empty = nullptr; d_carry = nullptr; d_gperm = nullptr;
     d_partial = nullptr;
@@ -139,10 +139,10 @@ void Built::free_device()
 
 void Workspace::free_all()
 {
-    if (M) hipFree(M);
-    if (dbl) hipFree(dbl);
-    if (flags) hipFree(flags);
-    if (host_pinned) hipHostFree(host_pinned);
+    if (M) (void)hipFree(M);
+    if (dbl) (void)hipFree(dbl);
+    if (flags) (void)hipFree(flags);
+    if (host_pinned) (void)hipHostFree(host_pinned);
     M = nullptr; dbl = nullptr; flags = nullptr; host_pinned = nullptr;
     M_cap = dbl_cap = 0;
 }
@@ -594,12 +594,12 @@ void fcoo_destroy(fcoo_tensor *t)
     if (!t) return;
     for (auto &row : t->b)
         for (auto &b : row) b.free_device();
-    for (auto &p : t->d_coo) if (p) hipFree(p);
-    if (t->d_coo_val) hipFree(t->d_coo_val);
+    for (auto &p : t->d_coo) if (p) (void)hipFree(p);
+    if (t->d_coo_val) (void)hipFree(t->d_coo_val);
     t->ws.free_all();
-    if (t->ev_dep) hipEventDestroy(t->ev_dep);
-    if (t->ev_solved) hipEventDestroy(t->ev_solved);
-    if (t->aux) hipStreamDestroy(t->aux);
+    if (t->ev_dep) (void)hipEventDestroy(t->ev_dep);
+    if (t->ev_solved) (void)hipEventDestroy(t->ev_solved);
+    if (t->aux) (void)hipStreamDestroy(t->aux);
     delete t;
 }
 

@@ -54,8 +54,8 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
         return fail(FCOO_ENOMEM, "autotune output (%lld x %d floats)", (long long)rows, R);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) hipEventDestroy(e0);
-        hipFree(out);
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(out);
         return fail(FCOO_EHIP, "hipEventCreate");
     }
     float bms = FLT_MAX;
@@ -79,9 +79,9 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
             btile = tiles[c];
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(out);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(out);
     if (rc) return rc;
     if (btile != tiles[ncand - 1]) {
         o.tile_nnz = btile;
