@@ -170,7 +170,7 @@ def kernel_symbol(op, R, N):
     np_ = (N - 1) if op == "mttkrp" else 1
     npt = np_ if np_ <= 3 else 0
     return (f"void fcoo::dev::seg_tile_kernel<float, 4, {lpn}, {npt}, false, "
-            f"{'true' if op == 'mttkrp' else 'false'}, false>(fcoo::dev::SegArgs)")
+            f"{'true' if op == 'mttkrp' else 'false'}, false, 1>(fcoo::dev::SegArgs)")
 
 
 def load_traffic(khash):
