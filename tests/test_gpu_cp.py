@@ -118,3 +118,21 @@ def test_cp_als_order4():
     t = synth.random_small([30, 20, 10, 8], 8000, seed=7)
     out, orc = _run_both(t, 6, 6)
     assert np.abs(np.array(out["fits"]) - np.array(orc["fits"])).max() <= 1e-3
+
+
+@pytest.mark.parametrize("R", [2, 5, 12, 24, 40, 64])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_cp_als_ranks_first_sweep_factors_and_fits(R, dtype):
+    # ranks that are not powers of two pad the row-solve tiles (R rounded up
+    # to 2..64); the first sweep's factors from the same start agree with
+    # the oracle's, and the fits track it
+    t = synth.random_small([120, 90, 70], 30000, seed=R)
+    out, orc = _run_both(t, R, 3, dtype=dtype, seed=R)
+    tol = 1e-4 if dtype == "f32" else 2e-2
+    if dtype == "f32":
+        out1, orc1 = _run_both(t, R, 1, dtype=dtype, seed=R)
+        for m in range(3):
+            assert rel_fro(from_dev(out1["factors"][m]), orc1["factors"][m]) <= tol
+    diffs = np.abs(np.array(out["fits"]) - np.array(orc["fits"]))
+    tag("R", R, dtype, "fits", out["fits"], "max diff", diffs.max())
+    assert diffs.max() <= 1e-3
