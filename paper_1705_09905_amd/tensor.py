@@ -162,8 +162,11 @@ class Tensor:
         L.check(L.fcoo_spmttkrp(self._h, int(mode), fp, dt, R, out.data_ptr(), _stream()))
         return out
 
-    def spttm(self, mode: int, U, out=None):
-        """Y = X x_mode U over the fibres of the other modes (nseg x R, float32)."""
+    def spttm(self, mode: int, U, out=None, return_fibres: bool = False):
+        """Y = X x_mode U over the fibres of the other modes (nseg x R, float32).
+        With return_fibres, also the fibres' coordinates (nseg x (N-1) int32,
+        the other modes in ascending order, lexicographically increasing):
+        returns (Y, fibres)."""
         torch = _torch()
         if U.dim() != 2 or U.shape[0] != self.dims[mode] or not U.is_contiguous() or not U.is_cuda:
             raise ValueError("U must be a contiguous CUDA dims[mode] x R matrix")
@@ -173,6 +176,11 @@ class Tensor:
             out = torch.empty((nseg, R), dtype=torch.float32, device="cuda")
         L.check(L.fcoo_spttm(self._h, int(mode), U.data_ptr(), _dtype_code(U), R, out.data_ptr(),
                              _stream()))
+        if return_fibres:
+            seg = np.empty((nseg, self.order - 1), np.int32)
+            L.check(L.fcoo_export(self._h, int(mode), OPS["ttm"], None, None, None, None, seg.ctypes.data,
+                                  None, None))
+            return out, seg
         return out
 
     def spttmc(self, mode: int, factors, out=None):

@@ -45,9 +45,11 @@ def _check_ttm(t, R, mode, L=16, T=4096, dtype="f32", seed=0, kind="normal", tol
     Ud = f32(U) if dtype == "f32" else bf16(U)
     tag("ttm", t.dims, t.nnz, "R", R, "mode", mode, "L", L, "T", T, dtype)
     h = Tensor(t.idx, t.vals, t.dims).build(mode, "ttm", threadlen=L, tile_nnz=T)
-    Y = from_dev(h.spttm(mode, to_dev(Ud, dtype)))
+    Yt, fibd = h.spttm(mode, to_dev(Ud, dtype), return_fibres=True)
+    Y = from_dev(Yt)
     fib, exp = cpu.ttm(t.dims, t.idx, f32(t.vals), Ud, mode)
     np.testing.assert_array_equal(h.export(mode, "ttm")["fibres"], fib)
+    np.testing.assert_array_equal(fibd, fib)
     if exact:
         np.testing.assert_array_equal(Y, exp)
     else:
