@@ -208,14 +208,24 @@ def run_extra(args, log):
     for m in range(t.order):
         h.build(m, "mttkrp", threadlen=args.threadlen, tile_nnz=args.tile)
     build_s = time.time() - t0
-    infos = [h.info(m) for m in range(t.order)]
     N = t.order
     init = synth.factors(t.dims, R, cfg, role="init")
+    layout = {}
+    if args.tile == 0:
+        # layout per mode (tile size, XCD blocks) chosen by timing SpMTTKRP
+        import torch
+        Ft = [torch.tensor(a.astype(np.float32), device="cuda") for a in init]
+        for m in range(N):
+            r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
+            layout[f"mode{m}"] = {"tile_nnz": r["tile_nnz"], "xcd_blocks": r["xcd_blocks"]}
+        del Ft
+        log(f"autotuned layout {layout}")
+    infos = [h.info(m) for m in range(t.order)]
     rec = {"metric": METRIC, "n_gpus": 1, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic", "build_s": round(build_s, 2),
            "config": {"workload": f"{t.name}: " + ("CP-ALS" if kind == "cpals" else "gradient CP (MSE, Adam)")
                       + f", R = {R}", "dims": t.dims, "nnz": t.nnz, "R": R,
-                      "threadlen": args.threadlen, "tile_nnz": args.tile}}
+                      "threadlen": args.threadlen, "tile_nnz": layout or args.tile}}
 
     def mttkrp_bytes(sf, own=False):
         b = 0
@@ -345,14 +355,16 @@ def main():
         for m in range(t.order):
             for op in ("mttkrp", "ttm"):
                 r = h.autotune(m, op, facs[max(Rs)], tiles=[2048, 4096, 8192])
-                tiles[f"{op}{m}"] = r["tile_nnz"]
+                tiles[f"{op}{m}"] = r["tile_nnz"] if r["xcd_blocks"] <= 1 else f"{r['tile_nnz']}/xcd{r['xcd_blocks']}"
         log(f"autotuned tile sizes {tiles} in {time.time() - t0:.1f}s")
     # the same builds sorted and encoded on the GPU (identical arrays): timed for the record
     torch.cuda.synchronize()
     t0 = time.time()
     for m in range(t.order):
         for op in ("mttkrp", "ttm"):
-            h.build(m, op, threadlen=args.threadlen, tile_nnz=h.info(m, op)["tile_nnz"], device=True)
+            inf = h.info(m, op)
+            h.build(m, op, threadlen=args.threadlen, tile_nnz=inf["tile_nnz"], device=True,
+                    xcd_blocks=inf["xcd_blocks"])
     torch.cuda.synchronize()
     dev_build_s = time.time() - t0
     log(f"F-COO built on the GPU (6 builds) in {dev_build_s:.2f}s")

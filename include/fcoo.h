@@ -72,6 +72,14 @@ typedef struct {
                         and holds about 32 bytes per nonzero of scratch while it
                         runs.  The per-nonzero arrays then live on the device only
                         (fcoo_export copies them back).  Exclusive with host_only. */
+    int xcd_blocks;  /* SpMTTKRP builds: 8 splits the nonzeros into 8 blocks of
+                        about Z/8 nonzeros by ranges of the largest product
+                        mode's index; block b leads the sort order, runs on
+                        XCD b (whose L2 then holds that mode's rows of the
+                        block), and writes partial rows summed at the end of
+                        each call.  A segment is then a (block, row) pair and
+                        fcoo_export's seg holds block * dims[mode] + row.
+                        0 or 1: off (default). */
 } fcoo_opts;
 
 /* Sizes of one built (op, mode). */
@@ -88,6 +96,8 @@ typedef struct {
     int32_t tile_nnz;
     int32_t order;
     int32_t on_device;    /* 1 if uploaded                                        */
+    int32_t xcd_blocks;   /* 1, or the number of XCD blocks (SpMTTKRP)           */
+    int32_t block_mode;   /* mode whose index ranges define the blocks, or -1    */
 } fcoo_info_t;
 
 /*
@@ -144,11 +154,13 @@ int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, fl
                 uint8_t *bf, uint32_t *sf, int32_t *seg, int32_t *tile_seg0, int32_t *perm);
 
 /*
- * fcoo_autotune -- choose the tile size of one built (op, mode) by timing:
- * each candidate tile_nnz is built (keeping the current threadlen, default
- * 16) and its operation run once to warm up, then `reps` times between two
- * HIP events on `stream`; the fastest build is left in place (the paper
- * tunes its launch shape per dataset, Sec. V, Table V).
+ * fcoo_autotune -- choose the layout of one (op, mode) by timing: each
+ * candidate tile_nnz, and for op = MTTKRP each with xcd_blocks 0 and 8, is
+ * built (on the GPU when the sort key fits 64 bits, else on the host; the
+ * current threadlen is kept, default 16) and its operation run once to warm
+ * up, then `reps` times between two HIP events on `stream`; the fastest
+ * build is left in place (the paper tunes its launch shape per dataset,
+ * Sec. V, Table V).
  *   factors  as fcoo_spmttkrp (op = MTTKRP) or factors[mode] = U (op = TTM);
  *            device data of `dtype`, R columns.
  *   tiles    host array of `ncand` candidate tile sizes (each a multiple of

@@ -35,7 +35,7 @@ ERROR_NAMES = {
 
 class fcoo_opts(C.Structure):
     _fields_ = [("threadlen", C.c_int), ("tile_nnz", C.c_int), ("host_only", C.c_int),
-                ("device", C.c_int)]
+                ("device", C.c_int), ("xcd_blocks", C.c_int)]
 
 
 class fcoo_info_t(C.Structure):
@@ -43,7 +43,7 @@ class fcoo_info_t(C.Structure):
                 ("ntiles", C.c_int64), ("nfix", C.c_int64), ("nempty", C.c_int64),
                 ("bytes_format", C.c_int64), ("bytes_device", C.c_int64),
                 ("threadlen", C.c_int32), ("tile_nnz", C.c_int32), ("order", C.c_int32),
-                ("on_device", C.c_int32)]
+                ("on_device", C.c_int32), ("xcd_blocks", C.c_int32), ("block_mode", C.c_int32)]
 
 
 class FcooError(RuntimeError):

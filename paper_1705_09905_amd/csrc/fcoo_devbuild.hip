@@ -30,13 +30,15 @@ struct KeyArgs {
     int width[kMaxOrder];            // bits of each
     int nmodes;
     int64_t nnz;
+    const int32_t *blk_of;           // XCD blocks: block of each index of bidx (else null)
+    const int32_t *bidx;             // coordinates of the block mode
 };
 
 __global__ __launch_bounds__(256) void key_kernel(KeyArgs a, uint64_t *__restrict__ key,
                                                   uint32_t *__restrict__ pos)
 {
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < a.nnz; e += (int64_t)gridDim.x * 256) {
-        uint64_t k = 0;
+        uint64_t k = a.blk_of ? (uint64_t)a.blk_of[a.bidx[e]] : 0;
         for (int i = 0; i < a.nmodes; ++i) {
             const int w = a.width[i];
             k = (w ? (k << w) : k) | (uint64_t)(uint32_t)a.idx[i][e];
@@ -115,6 +117,9 @@ struct SegArgsB {
     int nim;
     int32_t *seg;                    // nseg x nim
     int64_t nnz;
+    const int32_t *blk_of;           // XCD blocks (SpMTTKRP): row = block * rows + index
+    const int32_t *bidx;
+    int32_t rows;
 };
 
 __global__ __launch_bounds__(256) void seg_kernel(SegArgsB a)
@@ -124,6 +129,7 @@ __global__ __launch_bounds__(256) void seg_kernel(SegArgsB a)
         const int64_t g = a.cum[s] - 1;
         const int32_t e = a.perm[s];
         for (int q = 0; q < a.nim; ++q) a.seg[g * a.nim + q] = a.idx[a.im[q]][e];
+        if (a.blk_of) a.seg[g] += a.blk_of[a.bidx[e]] * a.rows;
     }
 }
 
@@ -186,7 +192,7 @@ int alloc_dev(T **dst, int64_t n, int64_t pad, hipStream_t s, int64_t *acct)
 
 }  // namespace
 
-int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, hipStream_t s)
+int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, int nblk, hipStream_t s)
 {
     const int N = t->order;
     const int64_t Z = t->nnz;
@@ -198,7 +204,10 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, hi
         if (op == FCOO_OP_MTTKRP) b.pmodes.push_back(m); else b.imodes.push_back(m);
     }
     if (op == FCOO_OP_MTTKRP) b.imodes.insert(b.imodes.begin(), mode); else b.pmodes.push_back(mode);
-    int total = 0, pbits = 0;
+    int rc = setup_blocks(t, b, nblk);
+    if (rc) return rc;
+    const bool blocked = b.nblk > 1;
+    int total = blocked ? bits_of(b.nblk) : 0, pbits = 0;
     dev::KeyArgs ka{};
     ka.nnz = Z;
     for (int m : b.imodes) { ka.idx[ka.nmodes] = nullptr; ka.width[ka.nmodes++] = bits_of(t->dims[m]); }
@@ -208,7 +217,7 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, hi
         return fail(FCOO_EUNSUPPORTED, "device build needs the sort key within 64 bits (%d bits)", total);
     if (Z == 0) return fail(FCOO_EUNSUPPORTED, "device build of an empty tensor (build it on the host)");
     if (Z > (int64_t)0x7fffffff) return fail(FCOO_EUNSUPPORTED, "device build supports Z < 2^31");
-    int rc = upload_coo(t, s);
+    rc = upload_coo(t, s);
     if (rc) return rc;
     {
         int i = 0;
@@ -227,6 +236,14 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, hi
     if ((rc = tmp.get(&k0, Z)) || (rc = tmp.get(&k1, Z)) || (rc = tmp.get(&p0, Z)) || (rc = tmp.get(&p1, Z)) ||
         (rc = tmp.get(&head, Z)) || (rc = tmp.get(&cum, Z)) || (rc = tmp.get(&hb, ntiles + 1)))
         return rc;
+
+    int32_t *blk_d = nullptr;
+    if (blocked) {
+        if ((rc = tmp.get(&blk_d, (int64_t)b.blk_of.size()))) return rc;
+        FCOO_HIP(hipMemcpyAsync(blk_d, b.blk_of.data(), b.blk_of.size() * 4, hipMemcpyHostToDevice, s));
+        ka.blk_of = blk_d;
+        ka.bidx = t->d_coo[b.bmode];
+    }
 
     // 1. keys and the stable radix sort
     hipLaunchKernelGGL(dev::key_kernel, dim3(grid_of(Z)), dim3(256), 0, s, ka, k0, p0);
@@ -301,6 +318,11 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, hi
     sa.nim = nim;
     sa.seg = segd;
     sa.nnz = Z;
+    if (blocked) {
+        sa.blk_of = blk_d;
+        sa.bidx = t->d_coo[b.bmode];
+        sa.rows = (int32_t)t->dims[mode];
+    }
     hipLaunchKernelGGL(dev::seg_kernel, dim3(grid_of(Z)), dim3(256), 0, s, sa);
     FCOO_HIP(hipGetLastError());
     b.seg.resize((size_t)nseg * nim);

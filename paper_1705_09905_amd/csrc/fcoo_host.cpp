@@ -126,6 +126,9 @@ int64_t Built::format_bytes() const
 
 void Built::free_device()
 {
+    if (d_bpart) (void)hipFree(d_bpart);
+    d_bpart = nullptr;
+    bpart_cap = 0;
     for (auto &p : d_pidx) { if (p) (void)hipFree(p); p = nullptr; }
     void *ptrs[] = {d_val, d_bf, d_sf, d_seg_row, d_tile_seg0, d_perm, d_fix, d_empty, d_carry,
                     d_gperm, d_partial};
@@ -218,10 +221,61 @@ int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factor
     return FCOO_OK;
 }
 
+// XCD blocks: the product mode with the most rows is split into nblk index
+// ranges holding about Z / nblk nonzeros each; block b's nonzeros lead the
+// sort order as a group, and its tiles are those that start inside it.
+int setup_blocks(const fcoo_tensor *t, Built &b, int nblk)
+{
+    b.nblk = 1;
+    b.bmode = -1;
+    b.blk_of.clear();
+    b.blk_ts.clear();
+    b.rows = b.op == FCOO_OP_MTTKRP ? t->dims[b.mode] : 0;
+    if (nblk <= 1) return FCOO_OK;
+    if (nblk != kXcds) return fail(FCOO_EINVAL, "xcd_blocks must be 0, 1 or %d (got %d)", kXcds, nblk);
+    if (b.op != FCOO_OP_MTTKRP) return fail(FCOO_EINVAL, "xcd_blocks applies to SpMTTKRP builds");
+    if ((int64_t)nblk * t->dims[b.mode] > (int64_t)0x7fffffff)
+        return fail(FCOO_EUNSUPPORTED, "xcd_blocks: %d x dims[mode] exceeds the int32 row range", nblk);
+    int bm = b.pmodes[0];
+    for (int m : b.pmodes) if (t->dims[m] > t->dims[bm]) bm = m;
+    const int64_t D = t->dims[bm], Z = t->nnz;
+    std::vector<int64_t> cnt(D, 0);
+    for (int64_t e = 0; e < Z; ++e) cnt[t->idx[bm][e]]++;
+    b.blk_of.resize(D);
+    std::vector<int64_t> zs(nblk + 1, 0);
+    int64_t before = 0;
+    for (int64_t i = 0; i < D; ++i) {
+        int blk = Z > 0 ? (int)((before * nblk) / Z) : 0;
+        if (blk >= nblk) blk = nblk - 1;
+        b.blk_of[i] = blk;
+        zs[blk + 1] += cnt[i];
+        before += cnt[i];
+    }
+    for (int k = 0; k < nblk; ++k) zs[k + 1] += zs[k];
+    const int64_t T = b.tile_nnz, ntiles = (Z + T - 1) / T;
+    b.blk_ts.assign(nblk + 1, 0);
+    for (int k = 1; k < nblk; ++k) {
+        int64_t ts = zs[k] / T;
+        if (ts > ntiles) ts = ntiles;
+        b.blk_ts[k] = ts < b.blk_ts[k - 1] ? b.blk_ts[k - 1] : ts;
+    }
+    b.blk_ts[nblk] = ntiles;
+    b.nblk = nblk;
+    b.bmode = bm;
+    return FCOO_OK;
+}
+
+int64_t Built::max_block_tiles() const
+{
+    int64_t m = 0;
+    for (int k = 0; k < nblk; ++k) m = blk_ts[k + 1] - blk_ts[k] > m ? blk_ts[k + 1] - blk_ts[k] : m;
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // the F-COO build for one (op, mode)
 // ---------------------------------------------------------------------------
-static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz)
+static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk)
 {
     const int N = t->order;
     const int64_t Z = t->nnz;
@@ -233,11 +287,15 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
         if (op == FCOO_OP_MTTKRP) b.pmodes.push_back(m); else b.imodes.push_back(m);
     }
     if (op == FCOO_OP_MTTKRP) b.imodes.insert(b.imodes.begin(), mode); else b.pmodes.push_back(mode);
+    int rc0 = setup_blocks(t, b, nblk);
+    if (rc0) return rc0;
+    const bool blocked = b.nblk > 1;
+    const int bbits = blocked ? bit_width(b.nblk) : 0;
 
-    // 1. stable lexicographic order of (index-mode tuple, product-mode tuple)
+    // 1. stable lexicographic order of (block, index-mode tuple, product-mode tuple)
     std::vector<int> order_modes(b.imodes);
     order_modes.insert(order_modes.end(), b.pmodes.begin(), b.pmodes.end());
-    int total_bits = 0, pbits = 0;
+    int total_bits = bbits, pbits = 0;
     for (int m : b.imodes) total_bits += bit_width(t->dims[m]);
     for (int m : b.pmodes) { int w = bit_width(t->dims[m]); total_bits += w; pbits += w; }
     std::vector<uint32_t> perm(Z);
@@ -247,7 +305,7 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
         key.resize(Z);
         parallel_chunks(Z, T, [&](int, int64_t lo, int64_t hi) {
             for (int64_t e = lo; e < hi; ++e) {
-                uint64_t k = 0;
+                uint64_t k = blocked ? (uint64_t)b.blk_of[t->idx[b.bmode][e]] : 0;
                 for (int m : order_modes) k = (bit_width(t->dims[m]) ? (k << bit_width(t->dims[m])) : k) | (uint64_t)t->idx[m][e];
                 key[e] = k;
                 perm[e] = (uint32_t)e;
@@ -257,6 +315,10 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
     } else {
         for (int64_t e = 0; e < Z; ++e) perm[e] = (uint32_t)e;
         std::stable_sort(perm.begin(), perm.end(), [&](uint32_t x, uint32_t y) {
+            if (blocked) {
+                const int bx = b.blk_of[t->idx[b.bmode][x]], by = b.blk_of[t->idx[b.bmode][y]];
+                if (bx != by) return bx < by;
+            }
             for (int m : order_modes) {
                 int32_t a = t->idx[m][x], c = t->idx[m][y];
                 if (a != c) return a < c;
@@ -278,10 +340,13 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
             for (size_t q = 0; q < b.pmodes.size(); ++q) b.pidx[q][s] = t->idx[b.pmodes[q]][e];
             bool h = (s == 0);
             if (!h) {
-                if (packed) h = pbits < 64 && (key[s] >> pbits) != (key[s - 1] >> pbits);
-                else
+                if (packed) {
+                    h = pbits < 64 && (key[s] >> pbits) != (key[s - 1] >> pbits);
+                } else {
+                    if (blocked) h = b.blk_of[t->idx[b.bmode][e]] != b.blk_of[t->idx[b.bmode][perm[s - 1]]];
                     for (int m : b.imodes)
-                        if (t->idx[m][e] != t->idx[m][perm[s - 1]]) { h = true; break; }
+                        if (!h && t->idx[m][e] != t->idx[m][perm[s - 1]]) { h = true; break; }
+                }
             }
             head[s] = h;
         }
@@ -317,6 +382,7 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
     for (int64_t g = 0; g < cnt; ++g) {
         const uint32_t e = perm[seg_start[g]];
         for (int q = 0; q < nim; ++q) b.seg[(size_t)g * nim + q] = t->idx[b.imodes[q]][e];
+        if (blocked) b.seg[g] += b.blk_of[t->idx[b.bmode][e]] * (int32_t)t->dims[mode];
     }
 
     // 4. carry fix-up list: a segment that is still open at the end of a tile
@@ -344,11 +410,13 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
         b.fix.push_back(out_row(cnt - 1));
     }
 
-    // 5. output rows of MTTKRP that no nonzero touches
+    // 5. output rows of MTTKRP that no nonzero touches (with XCD blocks: rows
+    //    of the nblk x dims[mode] partial output)
     if (op == FCOO_OP_MTTKRP) {
-        std::vector<uint8_t> present(t->dims[mode], 0);
+        const int64_t rows = (int64_t)b.nblk * t->dims[mode];
+        std::vector<uint8_t> present(rows, 0);
         for (int64_t g = 0; g < cnt; ++g) present[b.seg[g]] = 1;
-        for (int64_t i = 0; i < t->dims[mode]; ++i)
+        for (int64_t i = 0; i < rows; ++i)
             if (!present[i]) b.empty_rows.push_back((int32_t)i);
     }
     b.built = true;
@@ -379,9 +447,10 @@ void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::v
     }
     b.empty_rows.clear();
     if (op == FCOO_OP_MTTKRP) {
-        std::vector<uint8_t> present(t->dims[mode], 0);
+        const int64_t rows = (int64_t)b.nblk * t->dims[mode];
+        std::vector<uint8_t> present(rows, 0);
         for (int64_t g = 0; g < cnt; ++g) present[b.seg[g]] = 1;
-        for (int64_t i = 0; i < t->dims[mode]; ++i)
+        for (int64_t i = 0; i < rows; ++i)
             if (!present[i]) b.empty_rows.push_back((int32_t)i);
     }
 }
@@ -440,7 +509,7 @@ using namespace fcoo;
 
 extern "C" {
 
-int fcoo_version(void) { return 100; }
+int fcoo_version(void) { return 101; }
 
 const char *fcoo_last_error(void) { return fcoo::g_err.c_str(); }
 
@@ -502,6 +571,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     int tile_nnz = opts && opts->tile_nnz ? opts->tile_nnz : 4096;
     const bool host_only = opts && opts->host_only;
     const bool on_gpu = opts && opts->device;
+    const int nblk = opts ? opts->xcd_blocks : 0;
     if (host_only && on_gpu) return fail(FCOO_EINVAL, "host_only and device are exclusive");
     if (threadlen != 8 && threadlen != 16 && threadlen != 32 && threadlen != 64)
         return fail(FCOO_EINVAL, "threadlen %d not in {8, 16, 32, 64}", threadlen);
@@ -513,7 +583,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     int rc;
     if (on_gpu) {
         try {
-            rc = build_on_device(t, b, mode, op, threadlen, tile_nnz, (hipStream_t)stream);
+            rc = build_on_device(t, b, mode, op, threadlen, tile_nnz, nblk, (hipStream_t)stream);
         } catch (const std::bad_alloc &) {
             rc = fail(FCOO_ENOMEM, "device build (host side)");
         }
@@ -524,7 +594,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
         return rc;
     }
     try {
-        rc = build_host(t, b, mode, op, threadlen, tile_nnz);
+        rc = build_host(t, b, mode, op, threadlen, tile_nnz, nblk);
     } catch (const std::bad_alloc &) {
         b = Built();
         return fail(FCOO_ENOMEM, "host build");
@@ -554,6 +624,8 @@ int fcoo_info(const fcoo_tensor *t, int mode, int op, fcoo_info_t *info)
     info->tile_nnz = b->tile_nnz;
     info->order = t->order;
     info->on_device = b->on_device ? 1 : 0;
+    info->xcd_blocks = b->nblk;
+    info->block_mode = b->bmode;
     return FCOO_OK;
 }
 
@@ -606,6 +678,16 @@ void fcoo_destroy(fcoo_tensor *t)
 // ---------------------------------------------------------------------------
 // sparse operations: argument checks, then the HIP launchers
 // ---------------------------------------------------------------------------
+
+// XCD blocks: the partial output (nblk x rows x width floats) of this build
+static int prep_blocks(Built *b, TileProblem &p, hipStream_t s)
+{
+    if (b->nblk <= 1) return FCOO_OK;
+    int rc = ensure_device_floats(&b->d_bpart, &b->bpart_cap, (int64_t)b->nblk * b->rows * p.R, s);
+    if (rc) return rc;
+    p.bpart = b->d_bpart;
+    return FCOO_OK;
+}
 int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R, float *M,
                   void *stream)
 {
@@ -625,6 +707,7 @@ int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtyp
     p.out = M;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
+    if ((rc = prep_blocks(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -663,6 +746,7 @@ int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype,
     p.out = Y;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * W, s))) return rc;
     p.carry = b->d_carry;
+    if ((rc = prep_blocks(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -687,6 +771,7 @@ int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float 
     int rc;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
+    if ((rc = prep_blocks(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -716,6 +801,7 @@ int fcoo_spmttkrp_values(fcoo_tensor *t, int mode, const float *g, const void *c
     p.out = M;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
+    if ((rc = prep_blocks(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -742,6 +828,7 @@ int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, in
     p.inv_nnz = b->nnz ? (float)(1.0 / (double)b->nnz) : 0.f;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
+    if ((rc = prep_blocks(b, p, s))) return rc;
     if (loss) {
         if ((rc = ensure_device_doubles(&b->d_partial, &b->partial_cap, b->ntiles + 1, s))) return rc;
         p.partial = b->d_partial;

@@ -15,6 +15,7 @@ constexpr int kMaxOrder = 8;
 constexpr int kMaxR = 256;
 constexpr int kMaxKronWidth = 16384;   // SpTTMc output columns (prod of the product-mode ranks)
 constexpr int kBlock = 256;        // threads per workgroup of the tile kernels (4 waves)
+constexpr int kXcds = 8;           // XCDs of an MI355X: workgroup w runs on XCD w % 8
 
 // error reporting (thread-local message, negative code returned)
 int fail(int code, const char *fmt, ...);
@@ -35,6 +36,16 @@ struct Built {
     int op = 0, mode = 0, threadlen = 0, tile_nnz = 0;
     int64_t nnz = 0, nseg = 0, npart = 0, ntiles = 0;
     std::vector<int> imodes, pmodes;
+
+    // XCD blocks (SpMTTKRP): the nonzeros are split into nblk groups by ranges
+    // of product mode bmode's index (blk_of), each group leading the sort key;
+    // a segment is a (block, row) pair written to partial row block * I + row,
+    // and block b's tiles [blk_ts[b], blk_ts[b+1]) run on XCD b
+    int nblk = 1;
+    int bmode = -1;
+    int64_t rows = 0;                         // SpMTTKRP: dims[mode] (rows of the result)
+    std::vector<int32_t> blk_of;              // dims[bmode]: block of each index
+    std::vector<int64_t> blk_ts;              // nblk + 1 tile starts
 
     // F-COO arrays (Sec. IV-B) and per-segment / per-tile indexing
     std::vector<std::vector<int32_t>> pidx;   // |pmodes| x Z
@@ -65,10 +76,13 @@ struct Built {
     float *d_carry = nullptr;                 // 2 x ntiles x R floats
     int64_t carry_cap = 0;                    // floats
     float *d_gperm = nullptr;                 // Z floats (values in stored order)
+    float *d_bpart = nullptr;                 // XCD blocks: nblk x I x width partial outputs
+    int64_t bpart_cap = 0;                    // floats
     double *d_partial = nullptr;              // per-tile float64 partial sums
     int64_t partial_cap = 0;
 
     int64_t nfix() const { return (int64_t)fix.size() / 3; }
+    int64_t max_block_tiles() const;
     int64_t format_bytes() const;
     void free_device();
 };
@@ -118,7 +132,10 @@ int upload_i32(int32_t **dst, const std::vector<int32_t> &v, int64_t pad, hipStr
 // (heads_before[t] = heads before nonzero t * tile_nnz, t = 0 .. ntiles) and b.seg
 void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::vector<int64_t> &heads_before);
 // the F-COO build of one (op, mode) on the GPU (same arrays as the host build)
-int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, hipStream_t s);
+int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk,
+                    hipStream_t s);
+// XCD blocks of a SpMTTKRP build (nblk 0 / 1: none); needs b.op, b.mode, b.pmodes, b.tile_nnz
+int setup_blocks(const fcoo_tensor *t, Built &b, int nblk);
 int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
 
 // launchers implemented in the .hip files (return FCOO_OK or an error code)
@@ -136,6 +153,7 @@ struct TileProblem {
     double *partial = nullptr;       // per-tile partial losses (ntiles) or null
     hipEvent_t ev_before = nullptr;  // recorded around the tile kernel when set
     hipEvent_t ev_after = nullptr;
+    float *bpart = nullptr;          // XCD blocks: nblk x rows x R partial output (segments land here)
     // SpTTMc: Kronecker rows; R is then the output width prod kr[q]
     bool kron = false;
     int kr[kMaxOrder] = {};          // per product mode q: columns of its factor

@@ -64,6 +64,17 @@ __global__ __launch_bounds__(256) void fixup_kernel(const int32_t *__restrict__ 
     }
 }
 
+// XCD blocks: out[i][c] = sum over blocks b of part[b][i][c], in block order.
+__global__ __launch_bounds__(256) void reduce_blocks_kernel(const float *__restrict__ part, int nblk,
+                                                            int64_t n, float *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        float v = part[e];
+        for (int k = 1; k < nblk; ++k) v += part[(int64_t)k * n + e];
+        out[e] = v;
+    }
+}
+
 // Rows of an MTTKRP result that no nonzero touches are zero.
 __global__ __launch_bounds__(256) void zero_rows_kernel(const int32_t *__restrict__ rows, int64_t nrows,
                                                         int R, float *__restrict__ out)
@@ -183,7 +194,7 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.bf = b.d_bf;
         a.tile_seg0 = b.d_tile_seg0;
         a.seg_row = b.op == FCOO_OP_MTTKRP ? b.d_seg_row : nullptr;
-        a.out = p.out;
+        a.out = b.nblk > 1 ? p.bpart : p.out;
         a.carry_a = p.carry;
         a.carry_b = p.carry + b.ntiles * (int64_t)R;
         a.own = p.own;
@@ -220,7 +231,15 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
             return fail(FCOO_EUNSUPPORTED, "fused residual needs R <= %d for this dtype (R = %d)", rt, R);
         L.npt = np <= 3 ? np : 0;
         L.rowmap = b.op == FCOO_OP_MTTKRP;
-        L.grid = dim3((unsigned)b.ntiles, (unsigned)nrt, 1);
+        a.nblk = b.nblk;
+        a.rows_own = (int)b.rows;
+        int64_t gx = b.ntiles;
+        if (b.nblk > 1) {
+            for (int k = 0; k <= b.nblk; ++k) a.blk_ts[k] = b.blk_ts[k];
+            gx = (int64_t)kXcds * b.max_block_tiles();   // workgroup w: XCD w % 8, its block's tiles
+            if (gx < 1) gx = 1;
+        }
+        L.grid = dim3((unsigned)gx, (unsigned)nrt, 1);
         hipError_t e;
         if (p.ev_before) FCOO_HIP(hipEventRecord(p.ev_before, s));
         if (p.kron) e = p.dtype == FCOO_F32 ? seg_launch_f32_kron(L, s) : seg_launch_bf16_kron(L, s);
@@ -231,14 +250,21 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         const int64_t nfix = b.nfix();
         if (nfix > 0) {
             hipLaunchKernelGGL(dev::fixup_kernel, dim3((unsigned)nfix), dim3(256), 0, s, b.d_fix,
-                               a.carry_a, a.carry_b, b.ntiles, R, p.out);
+                               a.carry_a, a.carry_b, b.ntiles, R, a.out);
             FCOO_HIP(hipGetLastError());
         }
     }
+    float *outp = b.nblk > 1 ? p.bpart : p.out;
     const int64_t nempty = (int64_t)b.empty_rows.size();
     if (nempty > 0) {
         hipLaunchKernelGGL(dev::zero_rows_kernel, dim3(grid_for(nempty * R, 256)), dim3(256), 0, s,
-                           b.d_empty, nempty, R, p.out);
+                           b.d_empty, nempty, R, outp);
+        FCOO_HIP(hipGetLastError());
+    }
+    if (b.nblk > 1) {
+        const int64_t n = b.rows * (int64_t)R;
+        hipLaunchKernelGGL(dev::reduce_blocks_kernel, dim3(grid_for(n, 256 * 4)), dim3(256), 0, s, p.bpart,
+                           b.nblk, n, p.out);
         FCOO_HIP(hipGetLastError());
     }
     return FCOO_OK;

@@ -46,6 +46,7 @@ namespace fcoo {
 namespace dev {
 
 constexpr int kMaxNP = 7;
+constexpr int kXcdBlocks = 8;        // XCDs of an MI355X: workgroup w runs on XCD w % 8
 
 struct SegArgs {
     const int32_t *pidx[kMaxNP];     // product-mode index streams (stored order)
@@ -67,6 +68,11 @@ struct SegArgs {
     int nseg;                        // number of segments
     float inv_nnz;                   // RESID: 1 / Z
     int kr[kMaxNP];                  // KRON: columns of each product mode's factor (R = their product)
+    // XCD blocks: workgroup w runs tile blk_ts[w % 8] + w / 8 of block w % 8
+    // (none past blk_ts[w % 8 + 1]); output rows are block * rows_own + row
+    int64_t blk_ts[kXcdBlocks + 1];
+    int nblk;                        // 1: plain tile order
+    int rows_own;                    // RESID with blocks: rows of the index mode
 };
 
 template <int N, int I = 0, class F>
@@ -272,7 +278,14 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int q = lane / LPN, j = lane % LPN;
-    const int64_t tile = blockIdx.x;
+    int64_t tile = blockIdx.x;
+    if (A.nblk > 1) {
+        // XCD-aware order: every tile of block b runs on XCD b, whose L2 then
+        // holds that block's rows of the split product mode
+        const int x = (int)(blockIdx.x % kXcdBlocks);
+        tile = A.blk_ts[x] + (int64_t)(blockIdx.x / kXcdBlocks);
+        if (tile >= A.blk_ts[x + 1]) return;          // the whole workgroup leaves, before any barrier
+    }
     const int T = A.tile_nnz;
     const int S = T / (4 * Q);                        // run length of one lane group
     const int64_t t0 = tile * (int64_t)T;
@@ -298,6 +311,8 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
     }
     const int R = A.R;
     const uint64_t R4 = (uint64_t)R * sizeof(FT);
+    // RESID: factor row of the index mode for an output row (blocks add block * rows)
+    auto own_row = [&](int r) -> int64_t { return A.nblk > 1 ? (int64_t)(r % A.rows_own) : (int64_t)r; };
     const char *fb[NPM];
     uint64_t R4k[NPM];                                // KRON: row bytes of each product mode
     if constexpr (KRON) {
@@ -401,7 +416,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
         zero(own);
         if (g >= 0 && rs < re) {
             currow = A.seg_row[g];
-            load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)currow * R + colc, own);
+            load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + own_row(currow) * R + colc, own);
         }
     }
 
@@ -421,7 +436,7 @@ __global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
             ++g;
             if constexpr (ROWMAP) currow = A.seg_row[g];
             if constexpr (RESID)
-                load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + (int64_t)currow * R + colc, own);
+                load_row<FT, VW>(reinterpret_cast<const FT *>(A.own) + own_row(currow) * R + colc, own);
         }
     };
     auto step = [&](const float (&h)[AW], float v, uint64_t hm, int st, int n) {

@@ -1,8 +1,8 @@
-// Per-tensor tuning of the tile size of one (operation, mode): the paper tunes
-// its launch shape per dataset (Sec. V, Table V); here each candidate
-// tile_nnz is built, its operation is timed with HIP events on the caller's
-// stream, and the fastest build is kept.  Host code over the public entry
-// points.
+// Per-tensor tuning of one (operation, mode): the paper tunes its launch
+// shape per dataset (Sec. V, Table V); here each candidate tile size (and,
+// for SpMTTKRP, the layout with and without XCD blocks) is built, its
+// operation is timed with HIP events on the caller's stream, and the fastest
+// build is kept.  Host code over the public entry points.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -43,9 +43,24 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
     fcoo_info_t inf{};
     if (fcoo_info(t, mode, op, &inf) == FCOO_OK) threadlen = inf.threadlen;
 
-    // output large enough for either operation (TTM: nseg rows, independent of the tile size)
-    fcoo_opts o{threadlen, tiles[0], 0, 0};
-    int rc = fcoo_build(t, mode, op, &o, stream);
+    // candidates: each tile size, and for SpMTTKRP with and without XCD
+    // blocks; built on the GPU when the sort key allows it (same arrays)
+    struct Cand { int tile, xcd; };
+    std::vector<Cand> cands;
+    for (int c = 0; c < ncand; ++c) {
+        cands.push_back({tiles[c], 0});
+        if (op == FCOO_OP_MTTKRP && t->nnz > 0) cands.push_back({tiles[c], kXcds});
+    }
+    auto build = [&](const Cand &c) -> int {
+        fcoo_opts o{threadlen, c.tile, 0, t->nnz > 0 ? 1 : 0, c.xcd};
+        int r = fcoo_build(t, mode, op, &o, stream);
+        if (r == FCOO_EUNSUPPORTED && o.device) {   // sort key over 64 bits: host build
+            o.device = 0;
+            r = fcoo_build(t, mode, op, &o, stream);
+        }
+        return r;
+    };
+    int rc = build(cands[0]);
     if (rc) return rc;
     if ((rc = fcoo_info(t, mode, op, &inf))) return rc;
     const int64_t rows = op == FCOO_OP_MTTKRP ? t->dims[mode] : inf.nseg;
@@ -59,10 +74,9 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
         return fail(FCOO_EHIP, "hipEventCreate");
     }
     float bms = FLT_MAX;
-    int btile = tiles[0];
-    for (int c = 0; c < ncand && rc == FCOO_OK; ++c) {
-        o.tile_nnz = tiles[c];
-        if (c > 0 && (rc = fcoo_build(t, mode, op, &o, stream))) break;
+    size_t bi = 0;
+    for (size_t c = 0; c < cands.size() && rc == FCOO_OK; ++c) {
+        if (c > 0 && (rc = build(cands[c]))) break;
         if ((rc = run_op(t, mode, op, factors, dtype, R, out, stream))) break;   // warm-up
         if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(FCOO_EHIP, "hipEventRecord"); break; }
         for (int r = 0; r < reps && rc == FCOO_OK; ++r) rc = run_op(t, mode, op, factors, dtype, R, out, stream);
@@ -76,17 +90,15 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
         ms /= (float)reps;
         if (ms < bms) {
             bms = ms;
-            btile = tiles[c];
+            bi = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(out);
     if (rc) return rc;
-    if (btile != tiles[ncand - 1]) {
-        o.tile_nnz = btile;
-        if ((rc = fcoo_build(t, mode, op, &o, stream))) return rc;
-    }
+    if (bi != cands.size() - 1 && (rc = build(cands[bi]))) return rc;
+    fcoo_opts o{threadlen, cands[bi].tile, 0, 0, cands[bi].xcd};
     if (best) *best = o;
     if (best_ms) *best_ms = bms;
     return FCOO_OK;

@@ -77,18 +77,19 @@ class Tensor:
 
     # ---- build / inspect --------------------------------------------------
     def build(self, mode: int, op: str = "mttkrp", threadlen: int = 0, tile_nnz: int = 0,
-              host_only: bool = False, device: bool = False) -> "Tensor":
-        """F-COO encoding of (op, mode); device=True sorts and encodes on the GPU."""
-        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0)
+              host_only: bool = False, device: bool = False, xcd_blocks: int = 0) -> "Tensor":
+        """F-COO encoding of (op, mode); device=True sorts and encodes on the GPU;
+        xcd_blocks=8 (SpMTTKRP) splits the nonzeros into per-XCD blocks."""
+        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0, int(xcd_blocks))
         stream = C.c_void_p(0) if host_only else _stream()
         L.check(L.fcoo_build(self._h, int(mode), OPS[op], C.byref(o), stream))
         return self
 
     def autotune(self, mode: int, op: str, factors, tiles: Optional[Sequence[int]] = None,
                  reps: int = 3) -> Dict[str, float]:
-        """Time each candidate tile size for (op, mode) with these factors
-        (op 'ttm': factors[mode] is U) and keep the fastest build.  Returns
-        dict(tile_nnz, threadlen, ms)."""
+        """Time each candidate layout for (op, mode) with these factors (op
+        'ttm': factors[mode] is U; SpMTTKRP also tries XCD blocks) and keep
+        the fastest build.  Returns dict(tile_nnz, threadlen, xcd_blocks, ms)."""
         if op == "mttkrp":
             fp, R, dt = self._factors(factors, skip=mode)
         else:
@@ -101,7 +102,8 @@ class Tensor:
         ms = C.c_float()
         L.check(L.fcoo_autotune(self._h, int(mode), OPS[op], fp, dt, R, cand, 0 if tiles is None else len(tiles),
                                 int(reps), C.byref(best), C.byref(ms), _stream()))
-        return {"tile_nnz": int(best.tile_nnz), "threadlen": int(best.threadlen), "ms": float(ms.value)}
+        return {"tile_nnz": int(best.tile_nnz), "threadlen": int(best.threadlen),
+                "xcd_blocks": int(best.xcd_blocks), "ms": float(ms.value)}
 
     def info(self, mode: int, op: str = "mttkrp") -> Dict[str, int]:
         i = L.fcoo_info_t()

@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size and launch configurations: the Zipf(1.1)
 100,000 x 80,000 x 60,000 tensor with 20M nonzeros, SpMTTKRP and SpTTM in
-every mode at R = 16 and 32 (threadlen 16, each tile size the benchmark's
-autotuner picks from), against the float64 C oracle computing every output
+every mode at R = 16 and 32 (threadlen 16, each tile size and XCD-block
+layout the benchmark's autotuner picks from), against the float64 C oracle computing every output
 row; SpTTMc on sampled rows; plus CP-ALS sweeps (float32 and bfloat16
 factors) against the oracle's fits on the same tensor."""
 import numpy as np
@@ -36,11 +36,12 @@ def test_full_size_spmttkrp_spttm_all_modes(c2):
             expM = cpu.mttkrp(t.dims, t.idx, vals, F, m)
             fib, expY = cpu.ttm(t.dims, t.idx, vals, F[m], m)
             for T in (2048, 4096, 8192):
-                tag("full size mttkrp", m, "R", R, "tile", T)
-                h.build(m, "mttkrp", threadlen=16, tile_nnz=T)
-                err = rel_fro(from_dev(h.spmttkrp(m, Fd)), expM)
-                tag("rel err", err)
-                assert err <= TOL_F32
+                for xcd in (0, 8):
+                    tag("full size mttkrp", m, "R", R, "tile", T, "xcd blocks", xcd)
+                    h.build(m, "mttkrp", threadlen=16, tile_nnz=T, xcd_blocks=xcd, device=xcd > 0)
+                    err = rel_fro(from_dev(h.spmttkrp(m, Fd)), expM)
+                    tag("rel err", err)
+                    assert err <= TOL_F32
                 tag("full size ttm", m, "R", R, "tile", T)
                 h.build(m, "ttm", threadlen=16, tile_nnz=T)
                 Yd = from_dev(h.spttm(m, Fd[m]))

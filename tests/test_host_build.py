@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(_lib.lib, n), n
         assert getattr(_lib.lib, n) is not None
-    assert _lib.lib.fcoo_version() == 100
+    assert _lib.lib.fcoo_version() == 101
 
 
 def _build_both(t, mode, op, L, T):
@@ -140,3 +140,65 @@ def test_error_codes():
     rc = _lib.fcoo_create(2, None, 0, None, None, C.byref(C.c_void_p()))
     assert rc == _lib.FCOO_EINVAL
     assert b"dims" in _lib.fcoo_last_error()
+
+
+def _blocks_of(t, bm, nblk=8):
+    # the documented split: indices of mode bm in order, block = floor(nonzeros
+    # before the index * nblk / Z)
+    cnt = np.bincount(np.asarray(t.idx[bm], np.int64), minlength=t.dims[bm])
+    before = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    return np.minimum((before * nblk) // t.nnz, nblk - 1)
+
+
+@pytest.mark.parametrize("dims,Z,mode", [([40, 300, 200], 20000, 0), ([500, 30, 20], 12000, 1),
+                                          ([30, 40, 50, 60], 9000, 2), ([20, 1000], 5000, 0)])
+def test_xcd_blocks_layout(dims, Z, mode):
+    # the blocked order is the concatenation, block by block, of the reference
+    # encoding of each block's nonzeros; segments are (block, row) pairs
+    t = synth.random_small(dims, Z, seed=Z)
+    L, T = 16, 512
+    h = Tensor(t.idx, t.vals, t.dims).build(mode, "mttkrp", threadlen=L, tile_nnz=T, host_only=True,
+                                             xcd_blocks=8)
+    info = h.info(mode)
+    assert info["xcd_blocks"] == 8
+    pm = [m for m in range(len(dims)) if m != mode]
+    bm = info["block_mode"]
+    assert bm == max(pm, key=lambda m: (dims[m], -m))
+    blk = _blocks_of(t, bm)[np.asarray(t.idx[bm])]
+    perm, heads, rows = [], [], []
+    for b in range(8):
+        sel = np.nonzero(blk == b)[0]
+        if sel.size == 0:
+            continue
+        enc = ref.fcoo_encode(t.dims, [c[sel] for c in t.idx], t.vals[sel].astype(np.float32), mode,
+                              ref.OP_MTTKRP, L, T)
+        perm.append(sel[enc["perm"]])
+        heads.append(enc["head"])
+        rows.append(enc["seg_row"].astype(np.int64) + b * dims[mode])
+    perm = np.concatenate(perm)
+    head = np.concatenate(heads).astype(bool)
+    got = h.export(mode, "mttkrp")
+    np.testing.assert_array_equal(got["perm"], perm)
+    np.testing.assert_array_equal(got["val"], t.vals[perm].astype(np.float32))
+    for q, m in enumerate(pm):
+        np.testing.assert_array_equal(got["pidx"][q], np.asarray(t.idx[m])[perm])
+    np.testing.assert_array_equal(got["seg_row"], np.concatenate(rows))
+    bf = (np.cumsum(head) & 1).astype(np.uint8)
+    np.testing.assert_array_equal(got["bf"], np.packbits(bf, bitorder="little"))
+    ntiles = -(-Z // T)
+    np.testing.assert_array_equal(got["tile_seg0"], np.cumsum(head)[np.arange(ntiles) * T] - 1)
+    assert info["nseg"] == head.sum()
+    # about Z / 8 nonzeros per block
+    sizes = np.bincount(blk, minlength=8)
+    assert sizes.max() <= Z / 8 + np.bincount(np.asarray(t.idx[bm])).max() + 1
+
+
+def test_xcd_blocks_refusals():
+    t = synth.random_small([20, 30, 40], 500, seed=1)
+    h = Tensor(t.idx, t.vals, t.dims)
+    with pytest.raises(FcooError) as e:
+        h.build(0, "ttm", host_only=True, xcd_blocks=8)
+    assert e.value.code == _lib.FCOO_EINVAL
+    with pytest.raises(FcooError) as e:
+        h.build(0, "mttkrp", host_only=True, xcd_blocks=4)
+    assert e.value.code == _lib.FCOO_EINVAL
