@@ -13,7 +13,8 @@ oracle (its C loops for the sparse products):
   a few Adam steps.
 
 Generating a workload and running the oracle take minutes each, so these run
-only with FCOO_LARGE=1 in the environment."""
+only with FCOO_LARGE=1 in the environment.  Builds run on the GPU, in both
+layouts (plain and XCD-blocked) where the benchmark may use either."""
 import os
 
 import numpy as np
@@ -52,12 +53,15 @@ def _cp_case(cfg, R, sweeps, dtypes):
     orc = ref.cp_als(t.dims, t.idx, vals, R, init, sweeps, mttkrp=_oracle_mttkrp)
     tag("oracle fits", orc["fits"])
     h = Tensor(t.idx, t.vals, t.dims)
-    for dtype in dtypes:
-        out = cp_als(h, R, sweeps, init, dtype=dtype)
-        d = np.abs(np.array(out["fits"]) - np.array(orc["fits"]))
-        tag("cp-als", cfg, dtype, "fits", out["fits"], "max |fit - oracle|", d.max())
-        assert len(out["fits"]) == sweeps
-        assert d.max() <= 1e-3
+    for xcd in (0, 8):                           # both layouts the benchmark's autotuner picks from
+        for m in range(t.order):
+            h.build(m, device=True, xcd_blocks=xcd)
+        for dtype in dtypes:
+            out = cp_als(h, R, sweeps, init, dtype=dtype, build=False)
+            d = np.abs(np.array(out["fits"]) - np.array(orc["fits"]))
+            tag("cp-als", cfg, dtype, "xcd blocks", xcd, "fits", out["fits"], "max |fit - oracle|", d.max())
+            assert len(out["fits"]) == sweeps
+            assert d.max() <= 1e-3
 
 
 def test_order4_zipf_50M_cp_als_R32_ten_sweeps():
@@ -77,18 +81,18 @@ def test_gradient_cp_zipf_200M_R64():
     vals = f32(t.vals)
     init = [f32(a) for a in synth.factors(t.dims, R, cfg, role="init")]
     h = Tensor(t.idx, t.vals, t.dims)
-    for m in range(t.order):
-        h.build(m)
     # gradient at the start: kernel error (oracle on the stored factors) and,
     # for bfloat16, the end-to-end error (oracle on the float32 factors)
     loss32, g32 = cpu.mse_grad(t.dims, t.idx, vals, init)
-    for dtype in ("f32", "bf16"):
+    for dtype, xcd in (("f32", 0), ("bf16", 0), ("f32", 8)):
+        for m in range(t.order):
+            h.build(m, device=True, xcd_blocks=xcd)
         stored = init if dtype == "f32" else [bf16(a) for a in init]
         exp_loss, exp_g = (loss32, g32) if dtype == "f32" else cpu.mse_grad(t.dims, t.idx, vals, stored)
         masters = [to_dev(a).requires_grad_() for a in init]
         loss = CPMSELoss.apply(h, dtype, *masters)
         loss.backward()
-        tag("loss", dtype, loss.item(), "oracle", exp_loss)
+        tag("loss", dtype, "xcd blocks", xcd, loss.item(), "oracle", exp_loss)
         assert abs(loss.item() - exp_loss) <= 1e-5 * exp_loss
         for m in range(t.order):
             G = from_dev(masters[m].grad)
@@ -108,6 +112,8 @@ def test_gradient_cp_zipf_200M_R64():
         _, g = cpu.mse_grad(t.dims, t.idx, vals, po)
         po, mo, vo = ref.adam_step(po, g, mo, vo, s, lr=lr)
     fit_o = _observed_fit(t.idx, vals, po)
+    for m in range(t.order):
+        h.build(m, device=True)
     for dtype in ("f32", "bf16"):
         masters = [to_dev(a).requires_grad_() for a in init]
         opt = torch.optim.Adam(masters, lr=lr, betas=(0.9, 0.999), eps=1e-8)
