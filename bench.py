@@ -212,11 +212,14 @@ def run_extra(args, log):
     init = synth.factors(t.dims, R, cfg, role="init")
     layout = {}
     if args.tile == 0:
-        # layout per mode (tile size, XCD blocks) chosen by timing SpMTTKRP
+        # layout per mode (tile size, XCD blocks) chosen by timing SpMTTKRP;
+        # the fused residual kernel of gradient CP prefers other tile sizes
+        # than plain SpMTTKRP, so there only the XCD layout is chosen
         import torch
         Ft = [torch.tensor(a.astype(np.float32), device="cuda") for a in init]
+        cand = [2048, 4096, 8192] if kind == "cpals" else [4096]
         for m in range(N):
-            r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
+            r = h.autotune(m, "mttkrp", Ft, tiles=cand)
             layout[f"mode{m}"] = {"tile_nnz": r["tile_nnz"], "xcd_blocks": r["xcd_blocks"]}
         del Ft
         log(f"autotuned layout {layout}")

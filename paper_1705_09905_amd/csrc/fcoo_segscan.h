@@ -252,14 +252,21 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
     out.v = take_a ? a.v : b.v;
 }
 
+// Held to 168 VGPRs, i.e. 3 waves per SIMD (a couple of registers more
+// drops to 2 and removes a third of the gathers in flight), except where
+// that would spill: the one-lane residual form, and bfloat16 with a single
+// product mode (whose full gather batch at 2 waves beats a half batch at 3)
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>
-__global__ __launch_bounds__(256) void seg_tile_kernel(SegArgs A)
+__global__ __launch_bounds__(256, ((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1)
+void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
     constexpr int NPM = NP > 0 ? NP : kMaxNP;         // product modes held per step
     constexpr int RAWREGS = (int)(sizeof(Raw<FT, VW>) / 4);
     // gathers in flight per lane: about 64 registers of raw rows
-    constexpr int CH0 = NP > 0 ? pow2_floor(64 / (NPM * RAWREGS)) : 2;
+    // bfloat16 rows widen to 8 floats per lane: with two or more product modes
+    // half the batch keeps them at 3 waves per SIMD
+    constexpr int CH0 = NP > 0 ? pow2_floor((sizeof(FT) == 2 && NPM >= 2 ? 32 : 64) / (NPM * RAWREGS)) : 2;
     constexpr int CL = CH0 > LPN ? CH0 : LPN;         // steps per chunk (stream granule)
     constexpr int CH = CH0 < CL ? CH0 : CL;           // steps per gather batch
     constexpr int U = CL / LPN;                       // stream entries per lane per chunk
