@@ -252,21 +252,31 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
     out.v = take_a ? a.v : b.v;
 }
 
-// Held to 168 VGPRs, i.e. 3 waves per SIMD (a couple of registers more
-// drops to 2 and removes a third of the gathers in flight), except where
-// that would spill: the one-lane residual form, and bfloat16 with a single
-// product mode (whose full gather batch at 2 waves beats a half batch at 3)
+// Waves per SIMD.  The gathers' latency is what the waves wait on, so the
+// wave count is held up by launch bounds, with the gather batch (registers
+// of rows in flight per lane) sized to fit: float32 SpMTTKRP / SpTTM run 4
+// waves (128 VGPRs) with a half batch; bfloat16 with two or more product
+// modes, the fused residual and SpTTMc run 3 (168 VGPRs); bfloat16 with one
+// product mode keeps the full batch at 2 waves (faster than a half batch at
+// 3), and the one-lane residual form is left unconstrained.
+template <typename FT, int LPN, int NP, bool RESID, bool KRON>
+struct TileShape {
+    static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && !RESID && !KRON;
+    static constexpr int waves = F32PLAIN ? 4
+                               : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
+    // registers of raw rows per lane for one gather batch
+    static constexpr int batch_regs = (F32PLAIN || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
+};
+
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>
-__global__ __launch_bounds__(256, ((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1)
+__global__ __launch_bounds__(256, (TileShape<FT, LPN, NP, RESID, KRON>::waves))
 void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
     constexpr int NPM = NP > 0 ? NP : kMaxNP;         // product modes held per step
     constexpr int RAWREGS = (int)(sizeof(Raw<FT, VW>) / 4);
-    // gathers in flight per lane: about 64 registers of raw rows
-    // bfloat16 rows widen to 8 floats per lane: with two or more product modes
-    // half the batch keeps them at 3 waves per SIMD
-    constexpr int CH0 = NP > 0 ? pow2_floor((sizeof(FT) == 2 && NPM >= 2 ? 32 : 64) / (NPM * RAWREGS)) : 2;
+    // gathers in flight per lane: the batch that fits the wave count above
+    constexpr int CH0 = NP > 0 ? pow2_floor(TileShape<FT, LPN, NP, RESID, KRON>::batch_regs / (NPM * RAWREGS)) : 2;
     constexpr int CL = CH0 > LPN ? CH0 : LPN;         // steps per chunk (stream granule)
     constexpr int CH = CH0 < CL ? CH0 : CL;           // steps per gather batch
     constexpr int U = CL / LPN;                       // stream entries per lane per chunk
