@@ -254,15 +254,15 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 
 // Waves per SIMD.  The gathers' latency is what the waves wait on, so the
 // wave count is held up by launch bounds, with the gather batch (registers
-// of rows in flight per lane) sized to fit: float32 SpMTTKRP / SpTTM and the
-// float32 fused residual run 4 waves (128 VGPRs; the residual form spills a
-// few registers and is still faster) with a half batch; bfloat16 with two
-// or more product modes and SpTTMc run 3 (168 VGPRs); bfloat16 with one
-// product mode keeps the full batch at 2 waves (faster than a half batch at
-// 3), and the one-lane residual form is left unconstrained.
+// of rows in flight per lane) sized to fit: every float32 form runs 4 waves
+// (128 VGPRs; the fused residual spills a few registers there and is still
+// faster) with a half batch; bfloat16 with two or more product modes runs 3
+// (168 VGPRs); bfloat16 with one product mode keeps the full batch at 2
+// waves (faster than a half batch at 3), and the one-lane residual form is
+// left unconstrained.
 template <typename FT, int LPN, int NP, bool RESID, bool KRON>
 struct TileShape {
-    static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && !KRON && (!RESID || LPN > 1);
+    static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && (!RESID || LPN > 1);
     static constexpr int waves = F32PLAIN ? 4
                                : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
     // registers of raw rows per lane for one gather batch
