@@ -304,6 +304,7 @@ def main():
     ap.add_argument("--nnz", type=int, default=0, help="override the nonzero count (quick runs)")
     ap.add_argument("--threadlen", type=int, default=16)
     ap.add_argument("--tile", type=int, default=0, help="tile_nnz of every build (0: autotune per op and mode)")
+    ap.add_argument("--tile-ttm", type=int, default=0, help="with --tile: another tile_nnz for the SpTTM builds")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
@@ -348,7 +349,8 @@ def main():
     t0 = time.time()
     for m in range(t.order):
         for op in ("mttkrp", "ttm"):
-            h.build(m, op, threadlen=args.threadlen, tile_nnz=args.tile or 4096)
+            tile = (args.tile_ttm or args.tile) if op == "ttm" else args.tile
+            h.build(m, op, threadlen=args.threadlen, tile_nnz=tile or 4096)
     build_s = time.time() - t0
     log(f"F-COO built and uploaded (6 builds) in {build_s:.1f}s")
     tiles = {}
@@ -450,7 +452,14 @@ def main():
                 "avg_launch_ms": round(dc["ms"] / dc["n"], 4)}
     if tr is not None:
         rec = tr.get("kernels", {}).get(roofline["symbol"])
-        if rec is not None:
+        # the counters hold for the layout they were taken with (tile size, blocks)
+        lay = tr.get("layout", {}).get(dom[0])
+        same = lay is not None and all(
+            infos[(dom[0], m)]["tile_nnz"] == lay["tile_nnz"] and
+            infos[(dom[0], m)]["xcd_blocks"] == lay["xcd_blocks"] for m in range(t.order))
+        if rec is not None and not same:
+            roofline["traffic_note"] = f"counters were taken with layout {lay}, this run used another"
+        elif rec is not None:
             roofline["traffic"] = rec["bytes_per_launch"]
             roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     value = step_bytes / (ms_per_step / 1e3) / 1e9
@@ -471,7 +480,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{t.name}: SpMTTKRP + SpTTM, every mode, R in {Rs}",
                    "dims": t.dims, "nnz": t.nnz, "ranks": Rs, "threadlen": args.threadlen,
-                   "tile_nnz": tiles or args.tile},
+                   "tile_nnz": tiles or ({"mttkrp": args.tile, "ttm": args.tile_ttm} if args.tile_ttm else args.tile)},
         "gflops": round(step_flops / (ms_per_step / 1e3) / 1e9, 1),
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
         "spmttkrp_GBps": {str(R): round(mt[R]["bytes"] / mt[R]["ms"] / 1e6, 1) for R in Rs},
