@@ -3,8 +3,9 @@
 //   1. packed 64-bit key per nonzero (index modes, then product modes, each
 //      in ascending mode order, lower modes in the higher bits) and a stable
 //      radix sort of (key, input position) -- rocPRIM's device radix sort;
-//   2. gather of the product-mode indices, values and positions in sorted
-//      order, and the segment heads (index-mode part of the key changes);
+//   2. product-mode indices decoded from the sorted keys (their low bits),
+//      values gathered through the sorted positions, and the segment heads
+//      (index-mode part of the key changes);
 //   3. inclusive scan of the heads: segment ordinal of every nonzero;
 //   4. bf words (parity of the running head count, so the bit starts at 1
 //      and toggles at every head), sf words (any head in a partition), both
@@ -49,12 +50,12 @@ __global__ __launch_bounds__(256) void key_kernel(KeyArgs a, uint64_t *__restric
 }
 
 struct GatherArgs {
-    const int32_t *idx[kMaxOrder];   // coordinate arrays by mode
     const float *vals;
     const uint64_t *key;             // sorted keys
     const uint32_t *pos;             // input position of each sorted nonzero
     int32_t *pidx[kMaxOrder];        // per product mode q
-    int pm[kMaxOrder];               // mode of product mode q
+    int pshift[kMaxOrder];           // bit offset of product mode q in the key
+    int pwidth[kMaxOrder];           // its bits (0 for a mode of extent 1)
     int np;
     int pbits;                       // bits of the product-mode part of the key
     float *val;
@@ -67,11 +68,15 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a)
 {
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < a.nnz; s += (int64_t)gridDim.x * 256) {
         const uint32_t e = a.pos[s];
-        for (int q = 0; q < a.np; ++q) a.pidx[q][s] = a.idx[a.pm[q]][e];
+        const uint64_t k = a.key[s];
+        for (int q = 0; q < a.np; ++q) {
+            const int w = a.pwidth[q];
+            a.pidx[q][s] = w ? (int32_t)((k >> a.pshift[q]) & ((1ull << w) - 1)) : 0;
+        }
         a.val[s] = a.vals[e];
         a.perm[s] = (int32_t)e;
         int h = s == 0;
-        if (!h && a.pbits < 64) h = (a.key[s] >> a.pbits) != (a.key[s - 1] >> a.pbits);
+        if (!h && a.pbits < 64) h = (k >> a.pbits) != (a.key[s - 1] >> a.pbits);
         a.head[s] = h;
     }
 }
@@ -109,27 +114,30 @@ __global__ __launch_bounds__(256) void sf_kernel(const int32_t *__restrict__ hea
 }
 
 struct SegArgsB {
-    const int32_t *idx[kMaxOrder];   // coordinate arrays by mode
-    const int32_t *perm;
+    const uint64_t *key;             // sorted keys
     const int32_t *head;
     const int32_t *cum;
-    int im[kMaxOrder];               // index modes
+    int ishift[kMaxOrder];           // bit offset of index mode q in the key
+    int iwidth[kMaxOrder];           // its bits (0 for a mode of extent 1)
     int nim;
     int32_t *seg;                    // nseg x nim
     int64_t nnz;
-    const int32_t *blk_of;           // XCD blocks (SpMTTKRP): row = block * rows + index
-    const int32_t *bidx;
-    int32_t rows;
+    int bshift;                      // XCD blocks (SpMTTKRP): block number = key >> bshift,
+    int32_t rows;                    // row = block * rows + index (rows = 0: no blocks)
 };
 
+// Coordinates of every segment, decoded from the key of its head nonzero.
 __global__ __launch_bounds__(256) void seg_kernel(SegArgsB a)
 {
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < a.nnz; s += (int64_t)gridDim.x * 256) {
         if (!a.head[s]) continue;
         const int64_t g = a.cum[s] - 1;
-        const int32_t e = a.perm[s];
-        for (int q = 0; q < a.nim; ++q) a.seg[g * a.nim + q] = a.idx[a.im[q]][e];
-        if (a.blk_of) a.seg[g] += a.blk_of[a.bidx[e]] * a.rows;
+        const uint64_t k = a.key[s];
+        for (int q = 0; q < a.nim; ++q) {
+            const int w = a.iwidth[q];
+            a.seg[g * a.nim + q] = w ? (int32_t)((k >> a.ishift[q]) & ((1ull << w) - 1)) : 0;
+        }
+        if (a.rows) a.seg[g] += (int32_t)(a.bshift < 64 ? k >> a.bshift : 0) * a.rows;
     }
 }
 
@@ -259,15 +267,16 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
     // 2. sorted per-nonzero arrays (4 zero entries of padding, as uploaded by the host builder)
     int64_t acct = 0;
     dev::GatherArgs ga{};
-    for (int m = 0; m < N; ++m) ga.idx[m] = t->d_coo[m];
     ga.vals = t->d_coo_val;
     ga.key = k1;
     ga.pos = p1;
     ga.np = (int)b.pmodes.size();
-    for (int q = 0; q < ga.np; ++q) {
+    for (int q = ga.np - 1, sh = 0; q >= 0; --q) {   // last product mode in the lowest bits
         if ((rc = alloc_dev(&b.d_pidx[q], Z, 4, s, &acct))) return rc;
         ga.pidx[q] = b.d_pidx[q];
-        ga.pm[q] = b.pmodes[q];
+        ga.pwidth[q] = bits_of(t->dims[b.pmodes[q]]);
+        ga.pshift[q] = sh;
+        sh += ga.pwidth[q];
     }
     ga.pbits = pbits;
     if ((rc = alloc_dev(&b.d_val, Z, 4, s, &acct))) return rc;
@@ -310,17 +319,20 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
         return rc;
     }
     dev::SegArgsB sa{};
-    for (int m = 0; m < N; ++m) sa.idx[m] = t->d_coo[m];
-    sa.perm = b.d_perm;
+    sa.key = k1;
     sa.head = head;
     sa.cum = cum;
-    for (int q = 0; q < nim; ++q) sa.im[q] = b.imodes[q];
+    int sh = pbits;
+    for (int q = nim - 1; q >= 0; --q) {   // index modes above the product modes, last one lowest
+        sa.iwidth[q] = bits_of(t->dims[b.imodes[q]]);
+        sa.ishift[q] = sh;
+        sh += sa.iwidth[q];
+    }
     sa.nim = nim;
     sa.seg = segd;
     sa.nnz = Z;
     if (blocked) {
-        sa.blk_of = blk_d;
-        sa.bidx = t->d_coo[b.bmode];
+        sa.bshift = sh;
         sa.rows = (int32_t)t->dims[mode];
     }
     hipLaunchKernelGGL(dev::seg_kernel, dim3(grid_of(Z)), dim3(256), 0, s, sa);
