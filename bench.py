@@ -51,6 +51,34 @@ def op_bytes(op, Z, N, R, nseg, In, P, sf=4):
     return 4 * Z + 4 * Z + flags + Z * R * sf + 4 * nseg * R
 
 
+def compulsory_bytes(op, Z, N, R, nseg, In, P, distinct, mode, sf=4):
+    """Bytes one SpMTTKRP / SpTTM must move at the least: the streams and
+    the output as in op_bytes, but each distinct factor row read once."""
+    flags = (Z + 7) // 8 + 4 * ((P + 31) // 32)
+    if op == "mttkrp":
+        rows = sum(distinct[k] for k in range(N) if k != mode)
+        return 4 * Z * (N - 1) + 4 * Z + flags + 4 * nseg + rows * R * sf + 4 * In * R
+    return 8 * Z + flags + distinct[mode] * R * sf + 4 * nseg * R
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes / time) of a plain
+    1 GiB copy, for comparison with the kernels' traffic."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
 def op_flops(op, Z, N, R):
     return Z * R * N if op == "mttkrp" else 2 * Z * R
 
@@ -461,7 +489,20 @@ def main():
             roofline["traffic_note"] = f"counters were taken with layout {lay}, this run used another"
         elif rec is not None:
             roofline["traffic"] = rec["bytes_per_launch"]
+            roofline["traffic_GBps"] = round(rec["bytes_per_launch"] / (roofline["avg_launch_ms"] / 1e3) / 1e9, 1)
             roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    # the least bytes of the dominant kernel (each distinct factor row once),
+    # and a plain device copy's rate on this GPU
+    distinct = [int(np.count_nonzero(np.bincount(t.idx[k], minlength=t.dims[k]))) for k in range(t.order)]
+    comp = [compulsory_bytes(op, t.nnz, N, R, infos[(op, m)]["nseg"], t.dims[m], infos[(op, m)]["npart"],
+                             distinct, m) for (op, m, R) in launches if (op, R) == dom]
+    roofline["compulsory_bytes_per_launch"] = int(np.mean(comp))
+    roofline["compulsory_GBps"] = round(np.mean(comp) / (roofline["avg_launch_ms"] / 1e3) / 1e9, 1)
+    cbw = copy_bandwidth(torch)
+    roofline["copy_GBps_measured"] = round(cbw, 1)
+    for k in ("compulsory_GBps", "traffic_GBps"):
+        if k in roofline:
+            roofline[k.replace("GBps", "frac_of_copy")] = round(roofline[k] / cbw, 4)
     value = step_bytes / (ms_per_step / 1e3) / 1e9
     mt = {R: classes[("mttkrp", R)] for R in Rs}
     tt = {R: classes[("ttm", R)] for R in Rs}

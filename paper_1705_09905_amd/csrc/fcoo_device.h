@@ -179,6 +179,24 @@ __device__ __forceinline__ void store_row(float *__restrict__ p, const float (&v
     }
 }
 
+// The same, as streaming stores (bypass the cache's reuse policy): for
+// outputs written once and not read back by the kernel.
+template <int VW>
+__device__ __forceinline__ void store_row_stream(float *__restrict__ p, const float (&v)[VW])
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    if constexpr (VW % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < VW; k += 4) {
+            const f4 x = {v[k], v[k + 1], v[k + 2], v[k + 3]};
+            __builtin_nontemporal_store(x, reinterpret_cast<f4 *>(p + k));
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VW; ++k) __builtin_nontemporal_store(v[k], p + k);
+    }
+}
+
 template <int VW>
 __device__ __forceinline__ void load_out(const float *__restrict__ p, float (&v)[VW])
 {

@@ -360,7 +360,9 @@ void seg_tile_kernel(SegArgs A)
     // store the lane's AW columns of one output (or carry) row
     const int kstride = KB > 1 ? A.kr[np - 1] : 0;   // column distance between a lane's blocks
     auto store_acc = [&](float *rowp, const float (&v)[AW]) {
-        if constexpr (KB == 1) {
+        if constexpr (KB == 1 && !ROWMAP && !KRON) {
+            store_row_stream<VW>(rowp + col, v);      // SpTTM: one row per fibre, never re-read
+        } else if constexpr (KB == 1) {
             store_row<VW>(rowp + col, v);
         } else {
 #pragma unroll
