@@ -26,6 +26,13 @@ def cp_als(t: Tensor, R: int, sweeps: int, init: Sequence, dtype: str = "f32", t
     `sweeps` sweeps, or when tol > 0 and |fit change| < tol.
     Returns dict(factors=[torch], lam=torch (R,), fits=[float], used_pinv=[int bitmask])."""
     torch = _torch()
+    if dtype not in ("f32", "bf16"):
+        raise ValueError(f"dtype must be 'f32' or 'bf16' (got {dtype!r})")
+    if len(init) != t.order:
+        raise ValueError(f"need {t.order} initial factors")
+    for m, a in enumerate(init):
+        if tuple(a.shape) != (t.dims[m], R):
+            raise ValueError(f"initial factor {m} must be {t.dims[m]} x {R} (got {tuple(a.shape)})")
     if build:
         for m in range(t.order):
             inf = None

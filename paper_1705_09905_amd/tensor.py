@@ -32,6 +32,29 @@ def _dtype_code(t) -> int:
     raise TypeError(f"factor dtype {t.dtype} not supported (float32 or bfloat16)")
 
 
+def _out(out, shape, dtype):
+    """The caller's output tensor, checked (the library writes exactly
+    prod(shape) elements there), or a new one."""
+    torch = _torch()
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device="cuda")
+    if (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != dtype
+            or tuple(out.shape) != tuple(shape) or not out.is_contiguous()):
+        raise ValueError(f"out must be a contiguous CUDA {dtype} tensor of shape {tuple(shape)}")
+    return out
+
+
+def _index_column(c) -> np.ndarray:
+    """One mode's coordinates as int32, refusing values a cast would wrap."""
+    a = np.asarray(c)
+    if a.dtype.kind not in "iu":
+        raise TypeError(f"coordinates must be integers (got {a.dtype})")
+    if a.size and a.dtype.itemsize * 8 - (a.dtype.kind == "i") > 31:
+        if int(a.min()) < 0 or int(a.max()) > np.iinfo(np.int32).max:
+            raise ValueError("coordinates outside the int32 range")
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
 class Tensor:
     """A sparse tensor in COO form, with F-COO builds per (op, mode).
 
@@ -43,9 +66,9 @@ class Tensor:
         dims = [int(d) for d in dims]
         N = len(dims)
         if isinstance(coords, np.ndarray) and coords.ndim == 2:
-            cols = [np.ascontiguousarray(coords[:, m], dtype=np.int32) for m in range(N)]
+            cols = [_index_column(coords[:, m]) for m in range(N)]
         else:
-            cols = [np.ascontiguousarray(np.asarray(c), dtype=np.int32) for c in coords]
+            cols = [_index_column(c) for c in coords]
         if len(cols) != N:
             raise ValueError("coords must give one index array per mode")
         vals = np.ascontiguousarray(np.asarray(vals), dtype=np.float32)
@@ -159,8 +182,7 @@ class Tensor:
         """M = X_(mode) (Khatri-Rao product of the other factors), float32."""
         torch = _torch()
         fp, R, dt = self._factors(factors, skip=mode)
-        if out is None:
-            out = torch.empty((self.dims[mode], R), dtype=torch.float32, device="cuda")
+        out = _out(out, (self.dims[mode], R), torch.float32)
         L.check(L.fcoo_spmttkrp(self._h, int(mode), fp, dt, R, out.data_ptr(), _stream()))
         return out
 
@@ -174,8 +196,7 @@ class Tensor:
             raise ValueError("U must be a contiguous CUDA dims[mode] x R matrix")
         nseg = self.info(mode, "ttm")["nseg"]
         R = int(U.shape[1])
-        if out is None:
-            out = torch.empty((nseg, R), dtype=torch.float32, device="cuda")
+        out = _out(out, (nseg, R), torch.float32)
         L.check(L.fcoo_spttm(self._h, int(mode), U.data_ptr(), _dtype_code(U), R, out.data_ptr(),
                              _stream()))
         if return_fibres:
@@ -212,8 +233,7 @@ class Tensor:
             ptrs.append(f.data_ptr())
             ranks.append(int(f.shape[1]))
             W *= int(f.shape[1])
-        if out is None:
-            out = torch.empty((self.dims[mode], W), dtype=torch.float32, device="cuda")
+        out = _out(out, (self.dims[mode], W), torch.float32)
         rk = (C.c_int * self.order)(*ranks)
         L.check(L.fcoo_spttmc(self._h, int(mode), L.ptr_array(ptrs), dt, rk, out.data_ptr(), _stream()))
         return out
@@ -224,8 +244,7 @@ class Tensor:
         fp, R, dt = self._factors(factors, skip=mode)
         if g.dtype != torch.float32 or not g.is_cuda or g.numel() != self.nnz or not g.is_contiguous():
             raise ValueError("g must be a contiguous CUDA float32 vector of nnz values")
-        if out is None:
-            out = torch.empty((self.dims[mode], R), dtype=torch.float32, device="cuda")
+        out = _out(out, (self.dims[mode], R), torch.float32)
         L.check(L.fcoo_spmttkrp_values(self._h, int(mode), g.data_ptr(), fp, dt, R, out.data_ptr(),
                                        _stream()))
         return out
@@ -234,8 +253,7 @@ class Tensor:
         """xhat[e] = sum_r prod_m A_m[i_m(e), r] in input order (float32)."""
         torch = _torch()
         fp, R, dt = self._factors(factors)
-        if out is None:
-            out = torch.empty(self.nnz, dtype=torch.float32, device="cuda")
+        out = _out(out, (self.nnz,), torch.float32)
         L.check(L.fcoo_model_at_nnz(self._h, fp, dt, R, out.data_ptr(), _stream()))
         return out
 
@@ -244,17 +262,21 @@ class Tensor:
         `loss` (CUDA float64 scalar tensor) receives L when given."""
         torch = _torch()
         fp, R, dt = self._factors(factors)
-        if out is None:
-            out = torch.empty((self.dims[mode], R), dtype=torch.float32, device="cuda")
+        out = _out(out, (self.dims[mode], R), torch.float32)
+        if loss is not None and (not isinstance(loss, torch.Tensor) or not loss.is_cuda
+                                 or loss.dtype != torch.float64 or loss.numel() != 1):
+            raise ValueError("loss must be a CUDA float64 tensor of one element")
         lp = loss.data_ptr() if loss is not None else None
         L.check(L.fcoo_resid_spmttkrp(self._h, int(mode), fp, dt, R, out.data_ptr(), lp, _stream()))
         return out
 
     def gram(self, mode: int, A, out=None):
         torch = _torch()
+        if (not isinstance(A, torch.Tensor) or not A.is_cuda or A.dim() != 2
+                or A.shape[0] != self.dims[mode] or not A.is_contiguous()):
+            raise ValueError(f"A must be a contiguous CUDA {self.dims[mode]} x R matrix")
         R = int(A.shape[1])
-        if out is None:
-            out = torch.empty((R, R), dtype=torch.float64, device="cuda")
+        out = _out(out, (R, R), torch.float64)
         L.check(L.fcoo_gram(self._h, int(mode), A.data_ptr(), _dtype_code(A), R, out.data_ptr(),
                             _stream()))
         return out

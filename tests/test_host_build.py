@@ -202,3 +202,33 @@ def test_xcd_blocks_refusals():
     with pytest.raises(FcooError) as e:
         h.build(0, "mttkrp", host_only=True, xcd_blocks=4)
     assert e.value.code == _lib.FCOO_EINVAL
+
+
+def test_binding_refuses_wrapping_coordinates_and_bad_outputs():
+    import torch
+    from paper_1705_09905_amd.tensor import _out
+    dims = [4, 5, 6]
+    ok = [np.array([0, 3]), np.array([1, 4]), np.array([2, 5])]
+    Tensor(ok, np.ones(2), dims)                                     # int64 in range: accepted
+    with pytest.raises(ValueError):                                  # 2^32 + 1 would wrap to 1
+        Tensor([np.array([0, 2 ** 32 + 1]), ok[1], ok[2]], np.ones(2), dims)
+    with pytest.raises(ValueError):
+        Tensor([np.array([0, 2 ** 31], np.uint32), ok[1], ok[2]], np.ones(2), dims)
+    with pytest.raises(TypeError):
+        Tensor([np.array([0.0, 1.0]), ok[1], ok[2]], np.ones(2), dims)
+    with pytest.raises(FcooError):                                   # negative: the library's check
+        Tensor([np.array([0, -1], np.int32), ok[1], ok[2]], np.ones(2), dims)
+    with pytest.raises(ValueError):                                  # a host tensor is no output
+        _out(torch.empty((4, 8)), (4, 8), torch.float32)
+
+
+def test_cp_als_refuses_mis_shaped_initial_factors():
+    from paper_1705_09905_amd import cp_als
+    t = Tensor([np.array([0, 3]), np.array([1, 4]), np.array([2, 5])], np.ones(2), [4, 5, 6])
+    init = [np.ones((4, 3)), np.ones((5, 3)), np.ones((6, 2))]
+    with pytest.raises(ValueError):
+        cp_als(t, 3, 1, init, build=False)
+    with pytest.raises(ValueError):
+        cp_als(t, 3, 1, init[:2], build=False)
+    with pytest.raises(ValueError):
+        cp_als(t, 3, 1, [np.ones((4, 3)), np.ones((5, 3)), np.ones((6, 3))], dtype="f16", build=False)
