@@ -263,10 +263,11 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 template <typename FT, int LPN, int NP, bool RESID, bool KRON>
 struct TileShape {
     static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && (!RESID || LPN > 1);
-    static constexpr int waves = F32PLAIN ? 4
+    static constexpr bool B16ONE = sizeof(FT) == 2 && NP == 1 && !RESID && !KRON;
+    static constexpr int waves = F32PLAIN ? 4 : B16ONE ? 3
                                : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
     // registers of raw rows per lane for one gather batch
-    static constexpr int batch_regs = (F32PLAIN || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
+    static constexpr int batch_regs = (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
 };
 
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>
