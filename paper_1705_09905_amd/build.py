@@ -32,6 +32,7 @@ SOURCES = [
     "fcoo_cp.hip",
     "seg_f32.hip",
     "seg_bf16.hip",
+    "seg_bf16_half.hip",
     "seg_f32_resid.hip",
     "seg_bf16_resid.hip",
     "seg_f32_kron.hip",

@@ -117,6 +117,7 @@ template <> struct Raw<bf16raw, 8> { uint4 v; };
 template <> struct Raw<float, 1> { float v; };
 template <> struct Raw<bf16raw, 1> { uint32_t v; };
 template <> struct Raw<bf16raw, 2> { uint32_t v; };   // two consecutive bfloat16
+template <> struct Raw<bf16raw, 4> { uint2 v; };      // four consecutive bfloat16 (8-byte loads)
 
 template <typename FT, int VW>
 __device__ __forceinline__ void load_raw(const FT *__restrict__ p, Raw<FT, VW> &r)
@@ -125,6 +126,7 @@ __device__ __forceinline__ void load_raw(const FT *__restrict__ p, Raw<FT, VW> &
     else if constexpr (sizeof(FT) == 2 && VW == 8) r.v = *reinterpret_cast<const uint4 *>(p);
     else if constexpr (sizeof(FT) == 4 && VW == 1) r.v = *reinterpret_cast<const float *>(p);
     else if constexpr (sizeof(FT) == 2 && VW == 2) r.v = *reinterpret_cast<const uint32_t *>(p);
+    else if constexpr (sizeof(FT) == 2 && VW == 4) r.v = *reinterpret_cast<const uint2 *>(p);
     else r.v = (uint32_t)(*reinterpret_cast<const uint16_t *>(p));
 }
 
@@ -135,6 +137,7 @@ __device__ __forceinline__ void set_one(Raw<FT, VW> &r)
     else if constexpr (sizeof(FT) == 2 && VW == 8) r.v = make_uint4(0x3F803F80u, 0x3F803F80u, 0x3F803F80u, 0x3F803F80u);
     else if constexpr (sizeof(FT) == 4 && VW == 1) r.v = 1.f;
     else if constexpr (sizeof(FT) == 2 && VW == 2) r.v = 0x3F803F80u;
+    else if constexpr (sizeof(FT) == 2 && VW == 4) r.v = make_uint2(0x3F803F80u, 0x3F803F80u);
     else r.v = 0x3F80u;
 }
 
@@ -153,6 +156,9 @@ __device__ __forceinline__ void to_float(const Raw<FT, VW> &r, float (&out)[VW])
     } else if constexpr (sizeof(FT) == 2 && VW == 2) {
         out[0] = bf16_to_f32(r.v & 0xFFFFu);
         out[1] = bf16_to_f32(r.v >> 16);
+    } else if constexpr (sizeof(FT) == 2 && VW == 4) {
+        out[0] = bf16_to_f32(r.v.x & 0xFFFFu); out[1] = bf16_to_f32(r.v.x >> 16);
+        out[2] = bf16_to_f32(r.v.y & 0xFFFFu); out[3] = bf16_to_f32(r.v.y >> 16);
     } else {
         out[0] = bf16_to_f32(r.v);
     }

@@ -206,7 +206,10 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.tile_nnz = b.tile_nnz;
         a.nseg = (int)b.nseg;
         a.inv_nnz = p.inv_nnz;
-        const int V = p.dtype == FCOO_F32 ? 4 : 8;
+        // bfloat16 SpMTTKRP with two or more product modes and R <= 64: 4-column
+        // (8-byte) lane chunks, which hold twice the rows per gather batch
+        L.half = p.dtype == FCOO_BF16 && !resid && !p.kron && np >= 2 && R % 4 == 0 && R <= 64;
+        const int V = (p.dtype == FCOO_F32 || L.half) ? 4 : 8;
         // a lane's VW columns must lie in one row piece of the (last) factor
         L.vec = ((p.kron ? p.kr[np - 1] : R) % V) == 0;
         const int VW = L.vec ? V : 1;
@@ -244,6 +247,7 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         if (p.ev_before) FCOO_HIP(hipEventRecord(p.ev_before, s));
         if (p.kron) e = p.dtype == FCOO_F32 ? seg_launch_f32_kron(L, s) : seg_launch_bf16_kron(L, s);
         else if (p.dtype == FCOO_F32) e = resid ? seg_launch_f32_resid(L, s) : seg_launch_f32(L, s);
+        else if (L.half) e = seg_launch_bf16_half(L, s);
         else e = resid ? seg_launch_bf16_resid(L, s) : seg_launch_bf16(L, s);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
         if (p.ev_after) FCOO_HIP(hipEventRecord(p.ev_after, s));

@@ -15,6 +15,7 @@ struct SegLaunch {
     int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
     bool rowmap;     // output row = seg_row[segment] (SpMTTKRP) or the segment ordinal (SpTTM)
     int kb;          // SpTTMc: column blocks per lane (1, or KronBlock<FT>::KB)
+    bool half;       // bfloat16 SpMTTKRP in 4-column (8-byte) lane chunks
     dim3 grid;
 };
 
@@ -68,6 +69,30 @@ static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
     }
 }
 
+// bfloat16 SpMTTKRP (two or more product modes) in 4-column lane chunks:
+// half the row bytes per lane, so twice the rows per gather batch.
+template <typename FT, int LPN>
+static hipError_t seg_np_half(const SegLaunch &L, hipStream_t s)
+{
+    switch (L.npt) {
+        case 2: return seg_go<FT, 4, LPN, 2, false, true>(L, s);
+        case 3: return seg_go<FT, 4, LPN, 3, false, true>(L, s);
+        default: return seg_go<FT, 4, LPN, 0, false, true>(L, s);
+    }
+}
+
+template <typename FT>
+static hipError_t seg_dispatch_half(const SegLaunch &L, hipStream_t s)
+{
+    switch (L.lpn) {
+        case 1: return seg_np_half<FT, 1>(L, s);
+        case 2: return seg_np_half<FT, 2>(L, s);
+        case 4: return seg_np_half<FT, 4>(L, s);
+        case 8: return seg_np_half<FT, 8>(L, s);
+        default: return seg_np_half<FT, 16>(L, s);
+    }
+}
+
 // SpTTMc: Kronecker rows (generic path), output row = seg_row[segment].
 // Lanes per nonzero: 4 .. 64 (vector) or 64 (scalar); product modes 2, 3 or
 // a runtime count.
@@ -108,6 +133,7 @@ static hipError_t seg_dispatch_kron(const SegLaunch &L, hipStream_t s)
 
 hipError_t seg_launch_f32(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_bf16(const SegLaunch &L, hipStream_t s);
+hipError_t seg_launch_bf16_half(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_f32_resid(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_bf16_resid(const SegLaunch &L, hipStream_t s);
 hipError_t seg_launch_f32_kron(const SegLaunch &L, hipStream_t s);

@@ -256,29 +256,30 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 // wave count is held up by launch bounds, with the gather batch (registers
 // of rows in flight per lane) sized to fit: every float32 form runs 4 waves
 // (128 VGPRs; the fused residual spills a few registers there and is still
-// faster) with a half batch; bfloat16 with two or more product modes runs 3
-// (168 VGPRs); bfloat16 with one product mode keeps the full batch at 2
-// waves (faster than a half batch at 3), and the one-lane residual form is
-// left unconstrained.
-template <typename FT, int LPN, int NP, bool RESID, bool KRON>
+// faster) with a half batch, and so does bfloat16 in 4-column lane chunks
+// (8-byte row pieces: the same registers hold twice the rows); bfloat16 in
+// 8-column chunks runs 3 (133-168 VGPRs) with a half batch; the one-lane
+// residual form is left unconstrained.
+template <typename FT, int VW, int LPN, int NP, bool RESID, bool KRON>
 struct TileShape {
     static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && (!RESID || LPN > 1);
+    static constexpr bool B16HALF = sizeof(FT) == 2 && VW == 4 && NP >= 1 && !RESID && !KRON;
     static constexpr bool B16ONE = sizeof(FT) == 2 && NP == 1 && !RESID && !KRON;
-    static constexpr int waves = F32PLAIN ? 4 : B16ONE ? 3
+    static constexpr int waves = (F32PLAIN || B16HALF) ? 4 : B16ONE ? 3
                                : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
     // registers of raw rows per lane for one gather batch
-    static constexpr int batch_regs = (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
+    static constexpr int batch_regs = B16HALF ? 16 : (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
 };
 
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>
-__global__ __launch_bounds__(256, (TileShape<FT, LPN, NP, RESID, KRON>::waves))
+__global__ __launch_bounds__(256, (TileShape<FT, VW, LPN, NP, RESID, KRON>::waves))
 void seg_tile_kernel(SegArgs A)
 {
     constexpr int Q = 64 / LPN;                       // lane groups per wave
     constexpr int NPM = NP > 0 ? NP : kMaxNP;         // product modes held per step
     constexpr int RAWREGS = (int)(sizeof(Raw<FT, VW>) / 4);
     // gathers in flight per lane: the batch that fits the wave count above
-    constexpr int CH0 = NP > 0 ? pow2_floor(TileShape<FT, LPN, NP, RESID, KRON>::batch_regs / (NPM * RAWREGS)) : 2;
+    constexpr int CH0 = NP > 0 ? pow2_floor(TileShape<FT, VW, LPN, NP, RESID, KRON>::batch_regs / (NPM * RAWREGS)) : 2;
     constexpr int CL = CH0 > LPN ? CH0 : LPN;         // steps per chunk (stream granule)
     constexpr int CH = CH0 < CL ? CH0 : CL;           // steps per gather batch
     constexpr int U = CL / LPN;                       // stream entries per lane per chunk
