@@ -206,9 +206,10 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.tile_nnz = b.tile_nnz;
         a.nseg = (int)b.nseg;
         a.inv_nnz = p.inv_nnz;
-        // bfloat16 SpMTTKRP with two or more product modes and R <= 64: 4-column
-        // (8-byte) lane chunks, which hold twice the rows per gather batch
-        L.half = p.dtype == FCOO_BF16 && !resid && !p.kron && np >= 2 && R % 4 == 0 && R <= 64;
+        // bfloat16 SpMTTKRP with two product modes and R <= 64: 4-column (8-byte)
+        // lane chunks, which hold twice the rows per gather batch (with three
+        // or more, the batch per mode gets too short and 8-column chunks win)
+        L.half = p.dtype == FCOO_BF16 && !resid && !p.kron && np == 2 && R % 4 == 0 && R <= 64;
         const int V = (p.dtype == FCOO_F32 || L.half) ? 4 : 8;
         // a lane's VW columns must lie in one row piece of the (last) factor
         L.vec = ((p.kron ? p.kr[np - 1] : R) % V) == 0;

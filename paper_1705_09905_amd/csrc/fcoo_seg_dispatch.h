@@ -69,16 +69,12 @@ static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
     }
 }
 
-// bfloat16 SpMTTKRP (two or more product modes) in 4-column lane chunks:
+// bfloat16 SpMTTKRP (two product modes) in 4-column lane chunks:
 // half the row bytes per lane, so twice the rows per gather batch.
 template <typename FT, int LPN>
 static hipError_t seg_np_half(const SegLaunch &L, hipStream_t s)
 {
-    switch (L.npt) {
-        case 2: return seg_go<FT, 4, LPN, 2, false, true>(L, s);
-        case 3: return seg_go<FT, 4, LPN, 3, false, true>(L, s);
-        default: return seg_go<FT, 4, LPN, 0, false, true>(L, s);
-    }
+    return seg_go<FT, 4, LPN, 2, false, true>(L, s);
 }
 
 template <typename FT>
