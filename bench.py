@@ -21,6 +21,7 @@ import ctypes as C
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,10 +37,15 @@ KERNEL_SOURCES = ["fcoo_segscan.h", "fcoo_device.h", "fcoo_seg_dispatch.h", "fco
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources with comments and blank lines removed, so
+    stored counters stay tied to the code they were taken from."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1705_09905_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1705_09905_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

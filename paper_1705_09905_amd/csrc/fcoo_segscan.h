@@ -257,7 +257,7 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 // of rows in flight per lane) sized to fit: every float32 form runs 4 waves
 // (128 VGPRs; the fused residual spills a few registers there and is still
 // faster) with a half batch, and so does bfloat16 in 4-column lane chunks
-// (8-byte row pieces: the same registers hold twice the rows); bfloat16 in
+// (8-byte row pieces, so a quarter batch holds as many rows); bfloat16 in
 // 8-column chunks runs 3 (133-168 VGPRs) with a half batch; the one-lane
 // residual form is left unconstrained.
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool KRON>
