@@ -490,7 +490,7 @@ def main():
         lay = tr.get("layout", {}).get(dom[0])
         same = lay is not None and all(
             infos[(dom[0], m)]["tile_nnz"] == lay["tile_nnz"] and
-            infos[(dom[0], m)]["xcd_blocks"] == lay["xcd_blocks"] for m in range(t.order))
+            (infos[(dom[0], m)]["xcd_blocks"] > 1) == (lay["xcd_blocks"] > 1) for m in range(t.order))
         if rec is not None and not same:
             roofline["traffic_note"] = f"counters were taken with layout {lay}, this run used another"
         elif rec is not None:
