@@ -162,6 +162,19 @@ def test_bf16_factors():
     assert err <= TOL_BF16
 
 
+def test_bf16_lane_chunks_exact():
+    # bfloat16 SpMTTKRP takes 4-column lane chunks for two product modes and
+    # R <= 64 (R a multiple of 4; 1..16 lanes, ragged last lane group), else
+    # 8-column chunks; small integers are exact in bfloat16 and in the sums
+    t = synth.random_small([50, 40, 30], 20000, seed=16, value_kind="int")
+    for R in (4, 12, 20, 36, 60, 64, 72, 136):
+        for mode in range(3):
+            _check_mttkrp(t, R, mode, dtype="bf16", seed=R + mode, kind="int", exact=True)
+    t4 = synth.random_small([12, 10, 9, 8], 6000, seed=17, value_kind="int")
+    for mode in range(4):
+        _check_mttkrp(t4, 16, mode, dtype="bf16", seed=mode, kind="int", exact=True)
+
+
 def test_bitwise_repeatable():
     t = synth.zipf_tensor([5000, 4000, 3000], 300000, cfg=21)
     Tensor = _fcoo()
