@@ -254,6 +254,11 @@ int fcoo_model_at_nnz(fcoo_tensor *t, const void *const *factors, int dtype, int
  *   G     device, dims[mode] x R float32, written fully.
  *   loss  device double* or NULL; if given, receives L (computed in the same
  *         pass, reduced deterministically).
+ * Rank limit: one workgroup lane group holds a whole factor row (the residual
+ * needs the full dot product), so R <= 64 for float32 factors, and for
+ * bfloat16 R <= 128 when R is a multiple of 8, else R <= 64.  A larger R
+ * returns FCOO_EUNSUPPORTED; fcoo_model_at_nnz followed by
+ * fcoo_spmttkrp_values computes the same gradient at any R in [1, 256].
  * Requires fcoo_build(mode, FCOO_OP_MTTKRP).  Errors: as fcoo_spmttkrp.
  */
 int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,

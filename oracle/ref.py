@@ -437,7 +437,7 @@ def cp_fit(normX2: float, lam: np.ndarray, grams: Sequence[np.ndarray], M_last: 
 
 
 def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
-           storage: str = "f64", tol: float = 0.0, mttkrp=None):
+           storage: str = "f64", tol: float = 0.0, mttkrp=None, record=None):
     """Algorithm 1 for N modes (Gauss-Seidel order, newest factors used).
 
     For each sweep and each mode n:
@@ -451,6 +451,8 @@ def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
     A_0's initial value is never read (line 2 overwrites it first).
     `mttkrp(dims, idx, vals, factors, n)` may replace mttkrp_coo by another
     implementation of the same definition (the C loop, for large tensors).
+    `record`, a list or None, receives a copy (factors, lam) after every
+    sweep (observation only).
     Returns dict(factors, lam, fits, used_pinv[sweep][mode], grams)."""
     mttkrp = mttkrp_coo if mttkrp is None else mttkrp
     N = len(dims)
@@ -486,6 +488,8 @@ def cp_als(dims, idx, vals, R: int, init: Sequence[np.ndarray], sweeps: int,
             used.append(p)
         fits.append(cp_fit(normX2, lam, G, M, A[N - 1]))
         pinv_log.append(used)
+        if record is not None:
+            record.append(([a.copy() for a in A], lam.copy()))
         if tol > 0 and s > 0 and abs(fits[-1] - fits[-2]) < tol:
             break
     return dict(factors=A, lam=lam, fits=fits, used_pinv=pinv_log, grams=G)
@@ -551,10 +555,12 @@ def mse_grad(dims, idx, vals, factors) -> List[np.ndarray]:
     return model_adjoint(dims, idx, g, factors)
 
 
-def observed_fit(idx, vals, factors) -> float:
-    """fit over the observed entries: 1 - ||xhat - x|| / ||x||."""
+def observed_fit(idx, vals, factors, model=None) -> float:
+    """fit over the observed entries: 1 - ||xhat - x|| / ||x||.
+    `model(idx, factors)` may replace cp_model_at by another implementation
+    of the same definition (the C loop, for large tensors)."""
     x = np.asarray(vals, np.float64)
-    r = cp_model_at(idx, factors) - x
+    r = (cp_model_at if model is None else model)(idx, factors) - x
     return 1.0 - float(np.linalg.norm(r) / np.linalg.norm(x))
 
 

@@ -46,7 +46,12 @@ def cp_als(t: Tensor, R: int, sweeps: int, init: Sequence, dtype: str = "f32", t
     factors = []
     for m, a in enumerate(init):
         x = torch.as_tensor(np.asarray(a, dtype=np.float32) if not isinstance(a, torch.Tensor) else a)
-        factors.append(x.to(device="cuda", dtype=torch.float32).to(tdt).contiguous())
+        # a private copy: the sweeps overwrite the factors in place, and for a
+        # contiguous CUDA float32 input the conversions below return the
+        # caller's own tensor
+        f = torch.empty((t.dims[m], R), dtype=tdt, device="cuda")
+        f.copy_(x.to(device="cuda", dtype=torch.float32))
+        factors.append(f)
     code = _dtype_code(factors[0])
     lam = torch.zeros(R, dtype=torch.float64, device="cuda")
     grams = torch.zeros((t.order, R, R), dtype=torch.float64, device="cuda")

@@ -484,23 +484,22 @@ static int build_device(Built &b, hipStream_t s)
     return FCOO_OK;
 }
 
-static Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device)
+// The build of (op, mode), or NULL with *rc set: FCOO_EINVAL for a null
+// handle, a mode outside [0, order) or an unknown op; FCOO_ENOTBUILT when
+// that (op, mode) has no build (on the device, if need_device).
+static Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device, int *rc)
 {
-    if (!t) { fail(FCOO_EINVAL, "null handle"); return nullptr; }
-    if (mode < 0 || mode >= t->order) { fail(FCOO_EINVAL, "mode %d out of range", mode); return nullptr; }
-    if (op != FCOO_OP_MTTKRP && op != FCOO_OP_TTM) { fail(FCOO_EINVAL, "unknown op %d", op); return nullptr; }
+    if (!t) { *rc = fail(FCOO_EINVAL, "null handle"); return nullptr; }
+    if (mode < 0 || mode >= t->order) { *rc = fail(FCOO_EINVAL, "mode %d out of range", mode); return nullptr; }
+    if (op != FCOO_OP_MTTKRP && op != FCOO_OP_TTM) { *rc = fail(FCOO_EINVAL, "unknown op %d", op); return nullptr; }
     Built &b = t->b[op][mode];
     if (!b.built || (need_device && !b.on_device)) {
-        fail(FCOO_ENOTBUILT, "(op %d, mode %d) is not built%s", op, mode,
-             b.built ? " on the device" : "");
+        *rc = fail(FCOO_ENOTBUILT, "(op %d, mode %d) is not built%s", op, mode,
+                   b.built ? " on the device" : "");
         return nullptr;
     }
+    *rc = FCOO_OK;
     return &b;
-}
-
-Built *get_built_public(fcoo_tensor *t, int mode, int op, bool need_device)
-{
-    return get_built(t, mode, op, need_device);
 }
 
 }  // namespace fcoo
@@ -610,8 +609,9 @@ int fcoo_info(const fcoo_tensor *t, int mode, int op, fcoo_info_t *info)
 {
     clear_error();
     if (!info) return fail(FCOO_EINVAL, "info is NULL");
-    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false);
-    if (!b) return FCOO_ENOTBUILT == 0 ? 0 : (t ? FCOO_ENOTBUILT : FCOO_EINVAL);
+    int rc;
+    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false, &rc);
+    if (!b) return rc;
     info->nnz = b->nnz;
     info->nseg = b->nseg;
     info->npart = b->npart;
@@ -633,8 +633,9 @@ int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, fl
                 uint8_t *bf, uint32_t *sf, int32_t *seg, int32_t *tile_seg0, int32_t *perm)
 {
     clear_error();
-    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc;
+    const Built *b = get_built(const_cast<fcoo_tensor *>(t), mode, op, false, &rc);
+    if (!b) return rc;
     if (!b->host_arrays) {
         // built on the GPU: the per-nonzero arrays live on the device only
         const int64_t Z = b->nnz;
@@ -692,9 +693,10 @@ int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtyp
                   void *stream)
 {
     clear_error();
-    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
-    int rc = check_factors(t, mode, factors, dtype, R);
+    int rc;
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true, &rc);
+    if (!b) return rc;
+    rc = check_factors(t, mode, factors, dtype, R);
     if (rc) return rc;
     if (!M) return fail(FCOO_EINVAL, "M is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -717,8 +719,9 @@ int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype,
                 float *Y, void *stream)
 {
     clear_error();
-    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc;
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true, &rc);
+    if (!b) return rc;
     if (!ranks) return fail(FCOO_EINVAL, "ranks is NULL");
     int64_t W = 1;
     for (int m = 0; m < t->order; ++m) {
@@ -729,7 +732,7 @@ int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype,
         if (W > kMaxKronWidth)
             return fail(FCOO_EUNSUPPORTED, "SpTTMc width (product of the ranks) above %d", kMaxKronWidth);
     }
-    int rc = check_factors(t, mode, factors, dtype, 1);
+    rc = check_factors(t, mode, factors, dtype, 1);
     if (rc) return rc;
     if (!Y) return fail(FCOO_EINVAL, "Y is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -755,8 +758,9 @@ int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype,
 int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float *Y, void *stream)
 {
     clear_error();
-    Built *b = get_built(t, mode, FCOO_OP_TTM, true);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
+    int rc;
+    Built *b = get_built(t, mode, FCOO_OP_TTM, true, &rc);
+    if (!b) return rc;
     if ((!U && b->nnz) || (!Y && b->nseg)) return fail(FCOO_EINVAL, "U or Y is NULL");
     if (dtype != FCOO_F32 && dtype != FCOO_BF16) return fail(FCOO_EUNSUPPORTED, "unknown dtype %d", dtype);
     if (R < 1 || R > kMaxR) return fail(FCOO_EUNSUPPORTED, "R = %d outside [1, %d]", R, kMaxR);
@@ -768,7 +772,6 @@ int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float 
     p.dtype = dtype;
     p.R = R;
     p.out = Y;
-    int rc;
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
@@ -781,9 +784,10 @@ int fcoo_spmttkrp_values(fcoo_tensor *t, int mode, const float *g, const void *c
                          int dtype, int R, float *M, void *stream)
 {
     clear_error();
-    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
-    int rc = check_factors(t, mode, factors, dtype, R);
+    int rc;
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true, &rc);
+    if (!b) return rc;
+    rc = check_factors(t, mode, factors, dtype, R);
     if (rc) return rc;
     if (!M || (!g && b->nnz)) return fail(FCOO_EINVAL, "M or g is NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -811,9 +815,10 @@ int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, in
                         float *G, double *loss, void *stream)
 {
     clear_error();
-    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true);
-    if (!b) return t ? FCOO_ENOTBUILT : FCOO_EINVAL;
-    int rc = check_factors(t, -1, factors, dtype, R);
+    int rc;
+    Built *b = get_built(t, mode, FCOO_OP_MTTKRP, true, &rc);
+    if (!b) return rc;
+    rc = check_factors(t, -1, factors, dtype, R);
     if (rc) return rc;
     if (!G) return fail(FCOO_EINVAL, "G is NULL");
     hipStream_t s = (hipStream_t)stream;

@@ -1,6 +1,8 @@
 """Helpers shared by the GPU tests: tolerances, oracle inputs in the precision
 the device sees, and a printed tag before each GPU step."""
+import os
 import sys
+import time
 
 import numpy as np
 
@@ -9,9 +11,23 @@ TOL_F32 = 1e-5
 TOL_BF16 = 2e-2
 
 
+_PROGRESS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
+                         "gpu_test_progress.log")
+
+
 def tag(*parts):
-    print("[gpu]", *parts, flush=True)
+    """Print what names the GPU step about to run (test case, shape, seed);
+    the line also goes to a progress file, since pytest holds captured
+    output back until a test ends."""
+    line = " ".join(str(p) for p in ("[gpu]",) + parts)
+    print(line, flush=True)
     sys.stdout.flush()
+    try:
+        os.makedirs(os.path.dirname(_PROGRESS), exist_ok=True)
+        with open(_PROGRESS, "a") as f:
+            f.write(f"{time.strftime('%H:%M:%S')} {line}\n")
+    except OSError:
+        pass
 
 
 def f32(x):
@@ -41,3 +57,20 @@ def to_dev(a, dtype="f32"):
 def from_dev(t):
     import torch
     return t.detach().to(torch.float64).cpu().numpy()
+
+
+def sample_positions(Z, n, seed):
+    """Sorted distinct positions of a seeded sample of about n of Z nonzeros."""
+    g = np.random.default_rng(seed)
+    if n >= Z:
+        return np.arange(Z)
+    return np.unique(g.integers(0, Z, size=n))
+
+
+def model_values(idx, factors, lam, sel):
+    """The CP model sum_r lam_r prod_m A_m[i_m, r] at the nonzeros `sel`,
+    evaluated by the float64 oracle's C loop."""
+    from oracle import cpu
+    F = [np.asarray(a, np.float64) for a in factors]
+    F[-1] = F[-1] * np.asarray(lam, np.float64)[None, :]
+    return cpu.model_at([np.ascontiguousarray(i[sel]) for i in idx], F)

@@ -52,7 +52,7 @@ def test_resid_spmttkrp_and_loss(dims, Z, R):
             loss = torch.zeros((), dtype=torch.float64, device="cuda")
             tag("resid", dims, R, dtype, "mode", m)
             G = from_dev(h.resid_spmttkrp(m, [to_dev(f, dtype) for f in Fd], loss=loss))
-            assert rel_fro(G, exp_g[m]) <= 5 * TOL_F32, rel_fro(G, exp_g[m])
+            assert rel_fro(G, exp_g[m]) <= TOL_F32, rel_fro(G, exp_g[m])
             assert abs(loss.item() - exp_loss) <= 1e-5 * exp_loss
 
 
@@ -90,7 +90,7 @@ def test_autograd_mse_loss_vs_oracle_and_finite_differences():
     exp_g = ref.mse_grad(dims, t.idx, f32(t.vals), [f32(f) for f in F])
     assert abs(loss.item() - ref.mse_loss(t.idx, f32(t.vals), [f32(f) for f in F])) < 1e-6 * loss.item()
     for m in range(3):
-        assert rel_fro(from_dev(Fd[m].grad), exp_g[m]) <= 5 * TOL_F32
+        assert rel_fro(from_dev(Fd[m].grad), exp_g[m]) <= TOL_F32
     # central differences of the device loss itself (float32 path, coarse step)
     with torch.no_grad():
         for (m, i, r) in [(0, 3, 1), (1, 7, 2), (2, 9, 3)]:

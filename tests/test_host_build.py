@@ -142,6 +142,47 @@ def test_error_codes():
     assert b"dims" in _lib.fcoo_last_error()
 
 
+def test_mode_and_op_out_of_range_are_einval():
+    # every entry point that takes a mode (and an op) refuses one outside
+    # [0, order) or an unknown op with FCOO_EINVAL before any device work
+    h = Tensor([np.array([0, 1], np.int32), np.array([2, 0], np.int32), np.array([1, 1], np.int32)],
+               [1.0, 2.0], [3, 3, 2])
+    h.build(0, "mttkrp", host_only=True)
+    L = _lib
+    fac = L.ptr_array([1, 1, 1])
+    out = C.c_void_p(1)
+    info = L.fcoo_info_t()
+    ranks = (C.c_int * 3)(4, 4, 4)
+    for mode in (-1, 3, 7):
+        calls = {
+            "fcoo_build": lambda: L.fcoo_build(h.handle, mode, 0, None, None),
+            "fcoo_info": lambda: L.fcoo_info(h.handle, mode, 0, C.byref(info)),
+            "fcoo_export": lambda: L.fcoo_export(h.handle, mode, 0, None, None, None, None, None, None, None),
+            "fcoo_spmttkrp": lambda: L.fcoo_spmttkrp(h.handle, mode, fac, 0, 4, out, None),
+            "fcoo_spttm": lambda: L.fcoo_spttm(h.handle, mode, out, 0, 4, out, None),
+            "fcoo_spttmc": lambda: L.fcoo_spttmc(h.handle, mode, fac, 0, ranks, out, None),
+            "fcoo_spmttkrp_values": lambda: L.fcoo_spmttkrp_values(h.handle, mode, out, fac, 0, 4, out, None),
+            "fcoo_resid_spmttkrp": lambda: L.fcoo_resid_spmttkrp(h.handle, mode, fac, 0, 4, out, None, None),
+            "fcoo_gram": lambda: L.fcoo_gram(h.handle, mode, out, 0, 4, out, None),
+            "fcoo_autotune": lambda: L.fcoo_autotune(h.handle, mode, 0, fac, 0, 4, None, 0, 1, None, None,
+                                                     None),
+        }
+        for name, call in calls.items():
+            assert call() == L.FCOO_EINVAL, (name, mode)
+            assert b"out of range" in L.fcoo_last_error(), (name, mode)
+    for op in (-1, 2):
+        assert L.fcoo_build(h.handle, 0, op, None, None) == L.FCOO_EINVAL
+        assert L.fcoo_info(h.handle, 0, op, C.byref(info)) == L.FCOO_EINVAL
+        assert L.fcoo_export(h.handle, 0, op, None, None, None, None, None, None, None) == L.FCOO_EINVAL
+        assert b"unknown op" in L.fcoo_last_error()
+    # a valid but unbuilt (op, mode) is FCOO_ENOTBUILT, not FCOO_EINVAL
+    assert L.fcoo_info(h.handle, 1, 0, C.byref(info)) == L.FCOO_ENOTBUILT
+    assert L.fcoo_spttm(h.handle, 2, out, 0, 4, out, None) == L.FCOO_ENOTBUILT
+    # null handles
+    assert L.fcoo_info(None, 0, 0, C.byref(info)) == L.FCOO_EINVAL
+    assert L.fcoo_spmttkrp(None, 0, fac, 0, 4, out, None) == L.FCOO_EINVAL
+
+
 def _blocks_of(t, bm, nblk=8):
     # the documented split: indices of mode bm in order, block = floor(nonzeros
     # before the index * nblk / Z)

@@ -170,3 +170,81 @@ def test_adam_vs_torch_optim():
         opt.step()
     for a, b in zip(p, tp):
         np.testing.assert_allclose(a, b.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_observed_fit_hand_worked():
+    # the observed-entry fit of a 2 x 3 tensor with three nonzeros, worked by
+    # hand (tests/golden/observed_fit_2x3_handworked.json)
+    import json
+    import os
+    from conftest import GOLDEN
+    with open(os.path.join(GOLDEN, "observed_fit_2x3_handworked.json")) as f:
+        d = json.load(f)
+    idx = [np.array(c, np.int32) for c in d["idx"]]
+    A = [np.array(d["A0"], np.float64), np.array(d["A1"], np.float64)]
+    np.testing.assert_array_equal(ref.cp_model_at(idx, A), d["xhat"])
+    assert abs(ref.observed_fit(idx, d["vals"], A) - d["fit"]) <= 1e-10
+    # the same with the model from the C loop (the form the full-size tests use)
+    from oracle import cpu
+    assert abs(ref.observed_fit(idx, d["vals"], A, model=cpu.model_at) - d["fit"]) <= 1e-10
+    # an exact model fits 1, a zero model fits 0
+    assert ref.observed_fit(idx, d["xhat"], A) == 1.0
+    assert abs(ref.observed_fit(idx, d["vals"], [0 * a for a in A])) <= 1e-15
+
+
+def _one_sweep_by_hand(X, init, rnd):
+    """One Gauss-Seidel sweep of Algorithm 1 on a dense tensor, written with
+    other primitives than the oracle: MTTKRP as the dense unfolding times
+    scipy's Khatri-Rao product (Eq. 5), the R x R system by LAPACK's general
+    solver, column 2-norms by numpy, and the stored factor rounded by `rnd`
+    (a torch cast).  Returns the stored factors, lambda and the fit from the
+    dense residual."""
+    from scipy.linalg import khatri_rao
+    N = X.ndim
+    A = [rnd(a) for a in init]
+    for n in range(N):
+        Xn = np.reshape(np.moveaxis(X, n, 0), (X.shape[n], -1), order="F")
+        others = [m for m in range(N) if m != n]
+        K = A[others[-1]]
+        for m in reversed(others[:-1]):
+            K = khatri_rao(K, A[m])
+        M = Xn @ K
+        V = np.ones((A[0].shape[1],) * 2)
+        for m in others:
+            V = V * (A[m].T @ A[m])
+        An = np.linalg.solve(V, M.T).T
+        lam = np.linalg.norm(An, axis=0)
+        A[n] = rnd(An / lam)
+    Xh = ref.cp_full(A, lam)
+    return A, lam, 1.0 - np.linalg.norm(X - Xh) / np.linalg.norm(X)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_cp_als_storage_forms_match_one_sweep_by_hand(storage):
+    # the reduced-precision forms of the oracle's CP-ALS round each updated
+    # factor after normalisation and feed the rounded values to the next
+    # mode's product and Gram; pinned against a by-hand sweep that rounds
+    # through torch's own casts
+    def rnd(a):
+        tdt = torch.float32 if storage == "f32" else torch.bfloat16
+        return torch.tensor(a, dtype=torch.float64).to(tdt).to(torch.float64).numpy()
+
+    g = np.random.default_rng(21)
+    dims = [7, 6, 5]
+    X = np.where(g.random(dims) < 0.4, g.random(dims), 0.0)
+    idx = [c.astype(np.int32) for c in np.nonzero(X)]
+    vals = X[tuple(idx)]
+    R = 3
+    init = synth.small_factors(dims, R, seed=22)
+    out = ref.cp_als(dims, idx, vals, R, init, sweeps=1, storage=storage)
+    A, lam, fit = _one_sweep_by_hand(X, init, rnd)
+    for m in range(3):
+        np.testing.assert_allclose(out["factors"][m], A[m], rtol=1e-9, atol=1e-12)
+        # the stored factors are exactly representable in the storage type
+        np.testing.assert_array_equal(rnd(out["factors"][m]), out["factors"][m])
+        np.testing.assert_array_equal(out["grams"][m], out["factors"][m].T @ out["factors"][m])
+    np.testing.assert_allclose(out["lam"], lam, rtol=1e-9)
+    assert abs(out["fits"][0] - fit) <= 1e-9
+    # rounding changes the result: the float64 form differs from the stored one
+    f64 = ref.cp_als(dims, idx, vals, R, init, sweeps=1, storage="f64")
+    assert np.abs(f64["factors"][0] - out["factors"][0]).max() > 0
