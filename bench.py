@@ -8,11 +8,19 @@ Inputs and F-COO arrays are resident in HBM before the timed region.
 value = algorithmic bytes of the 12 operations / step time (GB/s): per
 nonzero the index and value streams, the bf / sf flags, one factor row per
 product mode gathered, plus the output rows written (the dense unfolding and
-Khatri-Rao product that the method avoids are not counted).
+Khatri-Rao product that the method avoids are not counted).  Gathered rows
+are often served by the caches, so this rate counts cache traffic too; the
+HBM fraction is taken from measured traffic instead (roofline below).
 
-Prints one JSON line.  The roofline object describes the dominant kernel (the
-SpMTTKRP or SpTTM tile kernel with the largest total time), timed alone with
-HIP events that the library records around each tile-kernel launch.
+The same JSON line carries CP-ALS (Algorithm 1) on the planted rank-16
+tensor 200,000 x 150,000 x 100,000 with 100M uniform nonzeros at R = 16,
+ten sweeps with float32 and with bfloat16 factor storage: seconds per sweep,
+the fit of every sweep, and (with the CPU leg) the float64 oracle's fits and
+the CP model at sampled nonzeros against the oracle's.
+
+The roofline object describes the dominant kernel (the SpMTTKRP or SpTTM
+tile kernel with the largest total time), timed alone with HIP events that
+the library records around each tile-kernel launch.
 """
 from __future__ import annotations
 
@@ -120,9 +128,21 @@ class HipEvents:
         self.events = []
 
 
-def cpu_baseline(t, Rs, sample_nnz, threads, cp=None):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(t, Rs, sample_nnz, threads, reps=5):
     """The float64 C oracle (plain COO loops, OpenMP) on a bounded sample of
-    the same workload: the first `sample_nnz` nonzeros of the shuffled list."""
+    the same workload: the first `sample_nnz` nonzeros of the shuffled list.
+    Per operation one warm-up run, then the median of `reps` timed runs."""
     from oracle import cpu
     import synth
     Zs = min(sample_nnz, t.nnz)
@@ -131,47 +151,50 @@ def cpu_baseline(t, Rs, sample_nnz, threads, cp=None):
     N = t.order
     total_bytes, total_s, used = 0, 0.0, 1
     groups = [cpu.ttm_group(t.dims, idx, m) for m in range(N)]
+
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), r
+
     for R in Rs:
         F = [f.astype(np.float32).astype(np.float64) for f in synth.factors(t.dims, R, WORKLOAD_CFG)]
         for m in range(N):
-            cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads)   # warm-up
-            t0 = time.perf_counter()
-            _, used = cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads, return_threads=True)
-            total_s += time.perf_counter() - t0
+            dt, (_, used) = med(lambda: cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads,
+                                                   return_threads=True))
+            total_s += dt
             nseg = len(np.unique(idx[m]))
             total_bytes += op_bytes("mttkrp", Zs, N, R, nseg, t.dims[m], -(-Zs // 16))
-            t0 = time.perf_counter()
-            fib, _, used2 = cpu.ttm(t.dims, idx, vals, F[m], m, group=groups[m], nthreads=threads,
-                                    return_threads=True)
-            total_s += time.perf_counter() - t0
+            dt, (fib, _, _) = med(lambda: cpu.ttm(t.dims, idx, vals, F[m], m, group=groups[m],
+                                                  nthreads=threads, return_threads=True))
+            total_s += dt
             total_bytes += op_bytes("ttm", Zs, N, R, fib.shape[0], t.dims[m], -(-Zs // 16))
-    rec = {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
-           "kind": "oracle",
-           "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
-                     f"every mode, R in {list(Rs)}, float64, {total_s:.2f} s timed "
-                     f"(fibre grouping excluded)"}
-    if cp is not None:
-        R, sweeps, init = cp
-        fits, s_per = cp_oracle(t, R, sweeps, init)
-        rec["cp_als"] = {"R": R, "sweeps": sweeps, "fits": [round(f, 6) for f in fits],
-                         "s_per_iter": round(s_per, 3), "note": "full workload, float64, C MTTKRP loops"}
-    return rec
+    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
+                      f"every mode, R in {list(Rs)}, float64; per operation 1 warm-up then the "
+                      f"median of {reps} runs, {total_s:.2f} s summed (fibre grouping excluded)"}
 
 
-def cp_oracle(t, R, sweeps, init):
+def cp_oracle(t, R, sweeps, init, record=None):
     """The float64 oracle's CP-ALS (Algorithm 1) on the full workload, with
     the C COO loop for its MTTKRPs, from the same initial factors."""
     from oracle import cpu, ref
     vals = t.vals.astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
     out = ref.cp_als(t.dims, t.idx, vals, R, [a.astype(np.float64) for a in init], sweeps,
-                     mttkrp=lambda d, i, v, F, n: cpu.mttkrp(d, i, v, F, n))
+                     mttkrp=lambda d, i, v, F, n: cpu.mttkrp(d, i, v, F, n), record=record)
     return out["fits"], (time.perf_counter() - t0) / sweeps
 
 
-def cp_gpu(h, t, R, sweeps, init, dtype):
+def cp_gpu(h, t, R, sweeps, init, dtype, keep_after=()):
     """CP-ALS sweeps on the device; wall time of every sweep (each call ends
-    with the 8-byte fit read-back)."""
+    with the 8-byte fit read-back).  Factors and lambda after the sweeps in
+    `keep_after` are copied to the host outside the timed calls."""
     import torch
     from paper_1705_09905_amd import _lib
     tdt = torch.float32 if dtype == "f32" else torch.bfloat16
@@ -182,7 +205,7 @@ def cp_gpu(h, t, R, sweeps, init, dtype):
     fit, used = C.c_double(), C.c_int()
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     code = _lib.FCOO_F32 if dtype == "f32" else _lib.FCOO_BF16
-    fits, secs = [], []
+    fits, secs, kept = [], [], {}
     torch.cuda.synchronize()
     for s in range(sweeps):
         t0 = time.perf_counter()
@@ -190,7 +213,87 @@ def cp_gpu(h, t, R, sweeps, init, dtype):
                                          1 if s else 0, C.byref(fit), C.byref(used), stream))
         secs.append(time.perf_counter() - t0)
         fits.append(float(fit.value))
-    return fits, secs
+        if s + 1 in keep_after:
+            kept[s + 1] = ([f.to(torch.float64).cpu().numpy() for f in F], lam.cpu().numpy())
+    return fits, secs, kept
+
+
+def model_sample(idx, factors, lam, sel):
+    """CP model sum_r lam_r prod_m A_m[i_m, r] at the sampled nonzeros, by the
+    float64 oracle's C loop (the CPU leg compares models, which are unique,
+    where factors are not)."""
+    from oracle import cpu
+    F = [np.asarray(a, np.float64) for a in factors]
+    F[-1] = F[-1] * np.asarray(lam, np.float64)[None, :]
+    return cpu.model_at([np.ascontiguousarray(i[sel]) for i in idx], F)
+
+
+def cp_planted(args, log, cpu_rec):
+    """CP-ALS (Algorithm 1) on the planted rank-16 tensor 200,000 x 150,000 x
+    100,000 with 100M uniform nonzeros, R = 16: float32 and bfloat16 factor
+    storage from the same start, seconds per sweep (median of sweeps 2..S)
+    and the fit of every sweep.  With the CPU leg (cpu_rec not None): the
+    float64 oracle's sweeps (its seconds per sweep are the CP-ALS CPU
+    baseline), the largest fit difference, and the relative error of the CP
+    model at sampled nonzeros after sweep 1 and sweep S.  ALS treats the
+    unsampled cells as zeros, so every fit here is tiny (about 7e-6): the
+    model at the nonzeros is what separates a right result from a wrong one."""
+    import torch
+    import synth
+    from paper_1705_09905_amd import Tensor
+    cfg, R, S = 3, 16, args.cp_sweeps
+    t0 = time.time()
+    t = synth.config_tensor(cfg)
+    log(f"generated {t.name} Z={t.nnz} in {time.time() - t0:.1f}s")
+    h = Tensor(t.idx, t.vals, t.dims)
+    init = synth.factors(t.dims, R, cfg, role="init")
+    t0 = time.time()
+    for m in range(t.order):
+        h.build(m, "mttkrp", threadlen=args.threadlen, tile_nnz=4096, device=True)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    layout = {}
+    Ft = [torch.tensor(a.astype(np.float32), device="cuda") for a in init]
+    for m in range(t.order):
+        # tile size and XCD layout per mode, chosen by timing SpMTTKRP (not timed below)
+        r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
+        layout[f"mode{m}"] = {"tile_nnz": r["tile_nnz"], "xcd_blocks": r["xcd_blocks"]}
+    del Ft
+    log(f"planted CP-ALS: built in {build_s:.2f}s, layout {layout}")
+    keep = (1, S) if cpu_rec is not None else ()
+    rec = {"workload": f"{t.name}: CP-ALS, R = {R}, {S} sweeps", "dims": t.dims, "nnz": t.nnz, "R": R,
+           "sweeps": S, "layout": layout, "device_build_s": round(build_s, 3)}
+    kept = {}
+    for dt in ("f32", "bf16"):
+        fits, secs, kept[dt] = cp_gpu(h, t, R, S, init, dt, keep_after=keep)
+        rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
+                   "s_per_iter_min": round(float(np.min(secs)), 6),
+                   "s_per_iter_max": round(float(np.max(secs)), 6),
+                   "fits": [float(f"{f:.6g}") for f in fits]}
+        log(f"cp-als {dt}: {rec[dt]['s_per_iter'] * 1e3:.3f} ms/sweep")
+    rec["bf16_speedup_vs_f32"] = round(rec["f32"]["s_per_iter"] / rec["bf16"]["s_per_iter"], 3)
+    del h
+    if cpu_rec is not None:
+        orec = []
+        t0 = time.time()
+        fits, s_per = cp_oracle(t, R, S, init, record=orec)
+        log(f"oracle CP-ALS in {time.time() - t0:.1f}s")
+        cpu_rec["cp_als"] = {"value": round(s_per, 3), "unit": "s/iter",
+                             "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                             "sample": f"the whole planted 100M tensor, {S} sweeps, float64, C MTTKRP loops",
+                             "fits": [float(f"{f:.6g}") for f in fits]}
+        sel = np.unique(np.random.default_rng(cfg).integers(0, t.nnz, size=args.cp_model_sample))
+        want = {s: model_sample(t.idx, orec[s - 1][0], orec[s - 1][1], sel) for s in keep}
+        for dt in ("f32", "bf16"):
+            rec[dt]["max_abs_fit_diff_vs_oracle"] = float(
+                f"{max(abs(a - b) for a, b in zip(rec[dt]['fits'], fits)):.3g}")
+            errs = {}
+            for s in keep:
+                got = model_sample(t.idx, kept[dt][s][0], kept[dt][s][1], sel)
+                errs[f"sweep{s}"] = float(f"{np.linalg.norm(got - want[s]) / np.linalg.norm(want[s]):.3g}")
+            rec[dt]["model_rel_err_vs_oracle"] = errs
+        rec["model_sample"] = f"{sel.size} seeded distinct nonzeros"
+    return rec
 
 
 def kernel_symbol(op, R, N):
@@ -276,7 +379,7 @@ def run_extra(args, log):
         sweeps = args.cp_sweeps
         rec["sweeps"] = sweeps
         for dt in ("f32", "bf16"):
-            fits, secs = cp_gpu(h, t, R, sweeps, init, dt)
+            fits, secs, _ = cp_gpu(h, t, R, sweeps, init, dt)
             s_it = float(np.median(secs[1:] if len(secs) > 1 else secs))
             B = mttkrp_bytes(4 if dt == "f32" else 2)
             rec[dt] = {"s_per_iter": round(s_it, 6), "fits": [round(f, 6) for f in fits],
@@ -340,12 +443,15 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="tile_nnz of every build (0: autotune per op and mode)")
     ap.add_argument("--tile-ttm", type=int, default=0, help="with --tile: another tile_nnz for the SpTTM builds")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000,
+                    help="nonzeros of the Zipf 20M tensor the CPU oracle baseline times")
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (scales traffic counters)")
-    ap.add_argument("--cp-rank", type=int, default=32)
-    ap.add_argument("--cp-sweeps", type=int, default=10)
+    ap.add_argument("--cp-sweeps", type=int, default=10,
+                    help="CP-ALS sweeps on the planted 100M tensor (0: skip that part)")
+    ap.add_argument("--cp-model-sample", type=int, default=1_000_000,
+                    help="nonzeros at which the CPU leg compares the CP model with the oracle's")
     ap.add_argument("--ttmc-rank", type=int, default=16, help="SpTTMc rank per mode (0: skip)")
     args = ap.parse_args()
 
@@ -462,53 +568,70 @@ def main():
         step_bytes += B
         step_flops += F
         d = float(np.mean(per[(op, m, R)]))
-        c = classes.setdefault((op, R), {"bytes": 0, "ms": 0.0, "n": 0})
+        c = classes.setdefault((op, R), {"bytes": 0, "ms": 0.0, "n": 0, "all": []})
         c["bytes"] += B
         c["ms"] += d
         c["n"] += 1
+        c["all"] += per[(op, m, R)]
         detail.append({"op": op, "mode": m, "R": R, "tile_ms": round(d, 4),
                        "GBps": round(B / d / 1e6, 1), "nseg": inf["nseg"], "nfix": inf["nfix"]})
+    for c in classes.values():
+        c["stats"] = {"mean": float(np.mean(c["all"])), "median": float(np.median(c["all"])),
+                      "min": float(np.min(c["all"])), "max": float(np.max(c["all"]))}
     if args.detail:
         for d in detail:
             log(json.dumps(d))
     dom = max(classes, key=lambda k: classes[k]["ms"])
     dc = classes[dom]
-    achieved = dc["bytes"] / dc["n"] / (dc["ms"] / dc["n"]) / 1e6     # GB/s per launch
+    avg_ms = dc["ms"] / dc["n"]
+    alg_bytes = int(dc["bytes"] / dc["n"])
     khash = kernel_hash()
     tr = load_traffic(khash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+    # the roofline of the dominant kernel: HBM bytes it moved per launch (copy-
+    # calibrated counters) over its average launch time, against 8 TB/s; the
+    # byte model's rate counts every gathered row, cache hits included, so it
+    # is reported beside it and not as an HBM fraction
+    roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": None,
                 "traffic": None,
                 "kernel": f"seg_tile_kernel ({'SpMTTKRP' if dom[0] == 'mttkrp' else 'SpTTM'}, R={dom[1]}, "
                           f"float32, per-mode launch)",
                 "symbol": kernel_symbol(dom[0], dom[1], t.order),
-                "bytes_per_launch": int(dc["bytes"] / dc["n"]),
-                "avg_launch_ms": round(dc["ms"] / dc["n"], 4)}
-    if tr is not None:
+                "avg_launch_ms": round(avg_ms, 4),
+                "launch_ms": {k: round(v, 4) for k, v in dc["stats"].items()},
+                "algorithmic_bytes_per_launch": alg_bytes,
+                "achieved_algorithmic_cache_inclusive": round(alg_bytes / avg_ms / 1e6, 1)}
+    if tr is None:
+        roofline["traffic_note"] = "no counters for this kernel source (hash mismatch or missing)"
+    else:
         rec = tr.get("kernels", {}).get(roofline["symbol"])
         # the counters hold for the layout they were taken with (tile size, blocks)
         lay = tr.get("layout", {}).get(dom[0])
         same = lay is not None and all(
             infos[(dom[0], m)]["tile_nnz"] == lay["tile_nnz"] and
             (infos[(dom[0], m)]["xcd_blocks"] > 1) == (lay["xcd_blocks"] > 1) for m in range(t.order))
-        if rec is not None and not same:
+        if rec is None:
+            roofline["traffic_note"] = "no counters for this kernel symbol"
+        elif not same:
             roofline["traffic_note"] = f"counters were taken with layout {lay}, this run used another"
-        elif rec is not None:
+        else:
             roofline["traffic"] = rec["bytes_per_launch"]
-            roofline["traffic_GBps"] = round(rec["bytes_per_launch"] / (roofline["avg_launch_ms"] / 1e3) / 1e9, 1)
+            roofline["achieved"] = round(rec["bytes_per_launch"] / (avg_ms / 1e3) / 1e9, 1)
+            roofline["frac"] = round(roofline["achieved"] / HBM_PEAK_GBPS, 4)
             roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+            if rec.get("limiter"):
+                roofline["limiter"] = rec["limiter"]
     # the least bytes of the dominant kernel (each distinct factor row once),
     # and a plain device copy's rate on this GPU
     distinct = [int(np.count_nonzero(np.bincount(t.idx[k], minlength=t.dims[k]))) for k in range(t.order)]
     comp = [compulsory_bytes(op, t.nnz, N, R, infos[(op, m)]["nseg"], t.dims[m], infos[(op, m)]["npart"],
                              distinct, m) for (op, m, R) in launches if (op, R) == dom]
     roofline["compulsory_bytes_per_launch"] = int(np.mean(comp))
-    roofline["compulsory_GBps"] = round(np.mean(comp) / (roofline["avg_launch_ms"] / 1e3) / 1e9, 1)
+    roofline["compulsory_GBps"] = round(np.mean(comp) / (avg_ms / 1e3) / 1e9, 1)
     cbw = copy_bandwidth(torch)
     roofline["copy_GBps_measured"] = round(cbw, 1)
-    for k in ("compulsory_GBps", "traffic_GBps"):
-        if k in roofline:
-            roofline[k.replace("GBps", "frac_of_copy")] = round(roofline[k] / cbw, 4)
+    roofline["compulsory_frac_of_copy"] = round(roofline["compulsory_GBps"] / cbw, 4)
+    if roofline["achieved"] is not None:
+        roofline["traffic_frac_of_copy"] = round(roofline["achieved"] / cbw, 4)
     value = step_bytes / (ms_per_step / 1e3) / 1e9
     mt = {R: classes[("mttkrp", R)] for R in Rs}
     tt = {R: classes[("ttm", R)] for R in Rs}
@@ -528,11 +651,16 @@ def main():
         "config": {"workload": f"{t.name}: SpMTTKRP + SpTTM, every mode, R in {Rs}",
                    "dims": t.dims, "nnz": t.nnz, "ranks": Rs, "threadlen": args.threadlen,
                    "tile_nnz": tiles or ({"mttkrp": args.tile, "ttm": args.tile_ttm} if args.tile_ttm else args.tile)},
+        "value_note": "algorithmic bytes (every gathered factor row counted, cache hits included) / step time",
         "gflops": round(step_flops / (ms_per_step / 1e3) / 1e9, 1),
-        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 2),
-        "spmttkrp_GBps": {str(R): round(mt[R]["bytes"] / mt[R]["ms"] / 1e6, 1) for R in Rs},
-        "spttm_GBps": {str(R): round(tt[R]["bytes"] / tt[R]["ms"] / 1e6, 1) for R in Rs},
+        "pct_hbm_peak": None if roofline["frac"] is None else round(100 * roofline["frac"], 2),
+        "pct_hbm_peak_basis": "measured HBM traffic of the dominant kernel / its launch time / 8 TB/s",
+        "spmttkrp_GBps_algorithmic": {str(R): round(mt[R]["bytes"] / mt[R]["ms"] / 1e6, 1) for R in Rs},
+        "spttm_GBps_algorithmic": {str(R): round(tt[R]["bytes"] / tt[R]["ms"] / 1e6, 1) for R in Rs},
         "spmttkrp_ms_per_mode": {str(R): round(mt[R]["ms"] / mt[R]["n"], 4) for R in Rs},
+        "spttm_ms_per_mode": {str(R): round(tt[R]["ms"] / tt[R]["n"], 4) for R in Rs},
+        "tile_ms_per_launch": {f"{op} R={R}": {k: round(v, 4) for k, v in c["stats"].items()}
+                               for (op, R), c in classes.items()},
         "roofline": roofline,
         "build_s": round(build_s, 2),
         "device_build_s": round(dev_build_s, 3),
@@ -571,28 +699,18 @@ def main():
                          "GBps_per_mode": [round(kb[m] / km[m] / 1e6, 1) for m in range(N)],
                          "GFLOPs_per_mode": [round(t.nnz * W * N / km[m] / 1e6, 1) for m in range(N)]}
         log(f"spttmc R={Rk}: {out['spttmc']['tile_ms_per_mode']} ms")
-    # CP-ALS sweeps on the same workload (every mode's MTTKRP build is resident)
-    Rc, Sc = args.cp_rank, args.cp_sweeps
-    init = synth.factors(t.dims, Rc, WORKLOAD_CFG, role="init")
-    cp_rec = {"R": Rc, "sweeps": Sc}
-    for dt in ("f32", "bf16"):
-        fits, secs = cp_gpu(h, t, Rc, Sc, init, dt)
-        cp_rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
-                      "fits": [round(f, 6) for f in fits]}
-    log(f"cp-als f32 {cp_rec['f32']['s_per_iter']} s/iter, bf16 {cp_rec['bf16']['s_per_iter']} s/iter")
-    out["cp_als"] = cp_rec
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         os.environ.setdefault("OMP_PROC_BIND", "close")
         t0 = time.time()
-        out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads, cp=(Rc, Sc, init))
-        of = out["cpu_baseline"]["cp_als"]["fits"]
-        for dt in ("f32", "bf16"):
-            gf = cp_rec[dt]["fits"]
-            cp_rec[dt]["max_abs_fit_diff_vs_oracle"] = round(max(abs(a - b) for a, b in zip(gf, of)), 6)
+        out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads)
         log(f"cpu baseline in {time.time() - t0:.1f}s")
     else:
         out["cpu_baseline"] = None
+    del h, facs, outs
+    torch.cuda.synchronize()
+    if args.cp_sweeps > 0:
+        out["cp_als"] = cp_planted(args, log, out["cpu_baseline"])
     print(json.dumps(out), flush=True)
 
 

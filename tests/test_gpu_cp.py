@@ -136,3 +136,24 @@ def test_cp_als_ranks_first_sweep_factors_and_fits(R, dtype):
     diffs = np.abs(np.array(out["fits"]) - np.array(orc["fits"]))
     tag("R", R, dtype, "fits", out["fits"], "max diff", diffs.max())
     assert diffs.max() <= 1e-3
+
+
+def test_cp_als_leaves_caller_init_unchanged():
+    # a contiguous CUDA float32 init is copied, not overwritten by the sweeps,
+    # so one init can start a float32 run and then a bfloat16 run
+    import torch
+    P = _lib()
+    t = synth.random_small([40, 30, 20], 4000, seed=11)
+    h = P.Tensor(t.idx, t.vals, t.dims)
+    init = [to_dev(f32(a)) for a in synth.small_factors(t.dims, 6, seed=11)]
+    keep = [a.clone() for a in init]
+    tag("cp_als init untouched")
+    r32 = P.cp_als(h, 6, 3, init, dtype="f32")
+    for a, b in zip(init, keep):
+        assert torch.equal(a, b)
+    r16 = P.cp_als(h, 6, 3, init, dtype="bf16")
+    for a, b in zip(init, keep):
+        assert torch.equal(a, b)
+    orc = ref.cp_als(t.dims, t.idx, f32(t.vals), 6, [from_dev(a) for a in keep], 3)
+    assert np.abs(np.array(r32["fits"]) - np.array(orc["fits"])).max() <= 1e-3
+    assert np.abs(np.array(r16["fits"]) - np.array(orc["fits"])).max() <= 1e-3
