@@ -80,6 +80,10 @@ typedef struct {
                         each call.  A segment is then a (block, row) pair and
                         fcoo_export's seg holds block * dims[mode] + row.
                         0 or 1: off (default). */
+    int xcd_mode;    /* with xcd_blocks: 1 + the product mode whose index
+                        ranges define the blocks (FCOO_EINVAL if it is not a
+                        product mode of the build); 0: the product mode with
+                        the most rows. */
 } fcoo_opts;
 
 /* Sizes of one built (op, mode). */

@@ -35,7 +35,7 @@ ERROR_NAMES = {
 
 class fcoo_opts(C.Structure):
     _fields_ = [("threadlen", C.c_int), ("tile_nnz", C.c_int), ("host_only", C.c_int),
-                ("device", C.c_int), ("xcd_blocks", C.c_int)]
+                ("device", C.c_int), ("xcd_blocks", C.c_int), ("xcd_mode", C.c_int)]
 
 
 class fcoo_info_t(C.Structure):

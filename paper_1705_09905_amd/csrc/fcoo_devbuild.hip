@@ -200,7 +200,7 @@ int alloc_dev(T **dst, int64_t n, int64_t pad, hipStream_t s, int64_t *acct)
 
 }  // namespace
 
-int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, int nblk, hipStream_t s)
+int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, int nblk, int xmode, hipStream_t s)
 {
     const int N = t->order;
     const int64_t Z = t->nnz;
@@ -212,7 +212,7 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
         if (op == FCOO_OP_MTTKRP) b.pmodes.push_back(m); else b.imodes.push_back(m);
     }
     if (op == FCOO_OP_MTTKRP) b.imodes.insert(b.imodes.begin(), mode); else b.pmodes.push_back(mode);
-    int rc = setup_blocks(t, b, nblk);
+    int rc = setup_blocks(t, b, nblk, xmode);
     if (rc) return rc;
     const bool blocked = b.nblk > 1;
     int total = blocked ? bits_of(b.nblk) : 0, pbits = 0;

@@ -224,7 +224,7 @@ int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factor
 // XCD blocks: the product mode with the most rows is split into nblk index
 // ranges holding about Z / nblk nonzeros each; block b's nonzeros lead the
 // sort order as a group, and its tiles are those that start inside it.
-int setup_blocks(const fcoo_tensor *t, Built &b, int nblk)
+int setup_blocks(const fcoo_tensor *t, Built &b, int nblk, int xmode)
 {
     b.nblk = 1;
     b.bmode = -1;
@@ -236,8 +236,14 @@ int setup_blocks(const fcoo_tensor *t, Built &b, int nblk)
     if (b.op != FCOO_OP_MTTKRP) return fail(FCOO_EINVAL, "xcd_blocks applies to SpMTTKRP builds");
     if ((int64_t)nblk * t->dims[b.mode] > (int64_t)0x7fffffff)
         return fail(FCOO_EUNSUPPORTED, "xcd_blocks: %d x dims[mode] exceeds the int32 row range", nblk);
-    int bm = b.pmodes[0];
-    for (int m : b.pmodes) if (t->dims[m] > t->dims[bm]) bm = m;
+    int bm = -1;
+    if (xmode >= 0) {
+        for (int m : b.pmodes) if (m == xmode) bm = m;
+        if (bm < 0) return fail(FCOO_EINVAL, "xcd_mode: mode %d is not a product mode of this build", xmode);
+    } else {
+        bm = b.pmodes[0];
+        for (int m : b.pmodes) if (t->dims[m] > t->dims[bm]) bm = m;
+    }
     const int64_t D = t->dims[bm], Z = t->nnz;
     std::vector<int64_t> cnt(D, 0);
     for (int64_t e = 0; e < Z; ++e) cnt[t->idx[bm][e]]++;
@@ -275,7 +281,8 @@ int64_t Built::max_block_tiles() const
 // ---------------------------------------------------------------------------
 // the F-COO build for one (op, mode)
 // ---------------------------------------------------------------------------
-static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk)
+static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk,
+                      int xmode)
 {
     const int N = t->order;
     const int64_t Z = t->nnz;
@@ -287,7 +294,7 @@ static int build_host(fcoo_tensor *t, Built &b, int mode, int op, int threadlen,
         if (op == FCOO_OP_MTTKRP) b.pmodes.push_back(m); else b.imodes.push_back(m);
     }
     if (op == FCOO_OP_MTTKRP) b.imodes.insert(b.imodes.begin(), mode); else b.pmodes.push_back(mode);
-    int rc0 = setup_blocks(t, b, nblk);
+    int rc0 = setup_blocks(t, b, nblk, xmode);
     if (rc0) return rc0;
     const bool blocked = b.nblk > 1;
     const int bbits = blocked ? bit_width(b.nblk) : 0;
@@ -571,6 +578,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     const bool host_only = opts && opts->host_only;
     const bool on_gpu = opts && opts->device;
     const int nblk = opts ? opts->xcd_blocks : 0;
+    const int xmode = opts ? opts->xcd_mode - 1 : -1;
     if (host_only && on_gpu) return fail(FCOO_EINVAL, "host_only and device are exclusive");
     if (threadlen != 8 && threadlen != 16 && threadlen != 32 && threadlen != 64)
         return fail(FCOO_EINVAL, "threadlen %d not in {8, 16, 32, 64}", threadlen);
@@ -582,7 +590,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     int rc;
     if (on_gpu) {
         try {
-            rc = build_on_device(t, b, mode, op, threadlen, tile_nnz, nblk, (hipStream_t)stream);
+            rc = build_on_device(t, b, mode, op, threadlen, tile_nnz, nblk, xmode, (hipStream_t)stream);
         } catch (const std::bad_alloc &) {
             rc = fail(FCOO_ENOMEM, "device build (host side)");
         }
@@ -593,7 +601,7 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
         return rc;
     }
     try {
-        rc = build_host(t, b, mode, op, threadlen, tile_nnz, nblk);
+        rc = build_host(t, b, mode, op, threadlen, tile_nnz, nblk, xmode);
     } catch (const std::bad_alloc &) {
         b = Built();
         return fail(FCOO_ENOMEM, "host build");

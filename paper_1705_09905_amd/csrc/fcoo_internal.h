@@ -133,9 +133,11 @@ int upload_i32(int32_t **dst, const std::vector<int32_t> &v, int64_t pad, hipStr
 void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::vector<int64_t> &heads_before);
 // the F-COO build of one (op, mode) on the GPU (same arrays as the host build)
 int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk,
-                    hipStream_t s);
-// XCD blocks of a SpMTTKRP build (nblk 0 / 1: none); needs b.op, b.mode, b.pmodes, b.tile_nnz
-int setup_blocks(const fcoo_tensor *t, Built &b, int nblk);
+                    int xmode, hipStream_t s);
+// XCD blocks of a SpMTTKRP build (nblk 0 / 1: none), split by ranges of product
+// mode xmode (-1: the product mode with the most rows); needs b.op, b.mode,
+// b.pmodes, b.tile_nnz
+int setup_blocks(const fcoo_tensor *t, Built &b, int nblk, int xmode);
 int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
 
 // launchers implemented in the .hip files (return FCOO_OK or an error code)

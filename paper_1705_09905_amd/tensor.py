@@ -100,10 +100,13 @@ class Tensor:
 
     # ---- build / inspect --------------------------------------------------
     def build(self, mode: int, op: str = "mttkrp", threadlen: int = 0, tile_nnz: int = 0,
-              host_only: bool = False, device: bool = False, xcd_blocks: int = 0) -> "Tensor":
+              host_only: bool = False, device: bool = False, xcd_blocks: int = 0,
+              xcd_mode: int = -1) -> "Tensor":
         """F-COO encoding of (op, mode); device=True sorts and encodes on the GPU;
-        xcd_blocks=8 (SpMTTKRP) splits the nonzeros into per-XCD blocks."""
-        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0, int(xcd_blocks))
+        xcd_blocks=8 (SpMTTKRP) splits the nonzeros into per-XCD blocks by
+        ranges of product mode xcd_mode (-1: the one with the most rows)."""
+        o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0, int(xcd_blocks),
+                        int(xcd_mode) + 1)
         stream = C.c_void_p(0) if host_only else _stream()
         L.check(L.fcoo_build(self._h, int(mode), OPS[op], C.byref(o), stream))
         return self

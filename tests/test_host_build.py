@@ -191,20 +191,22 @@ def _blocks_of(t, bm, nblk=8):
     return np.minimum((before * nblk) // t.nnz, nblk - 1)
 
 
-@pytest.mark.parametrize("dims,Z,mode", [([40, 300, 200], 20000, 0), ([500, 30, 20], 12000, 1),
-                                          ([30, 40, 50, 60], 9000, 2), ([20, 1000], 5000, 0)])
-def test_xcd_blocks_layout(dims, Z, mode):
+@pytest.mark.parametrize("dims,Z,mode,xmode", [([40, 300, 200], 20000, 0, -1), ([500, 30, 20], 12000, 1, -1),
+                                                ([30, 40, 50, 60], 9000, 2, -1), ([20, 1000], 5000, 0, -1),
+                                                ([40, 300, 200], 20000, 0, 2), ([30, 40, 50, 60], 9000, 2, 1)])
+def test_xcd_blocks_layout(dims, Z, mode, xmode):
     # the blocked order is the concatenation, block by block, of the reference
-    # encoding of each block's nonzeros; segments are (block, row) pairs
+    # encoding of each block's nonzeros; segments are (block, row) pairs; the
+    # blocks are ranges of the requested product mode, else the largest one
     t = synth.random_small(dims, Z, seed=Z)
     L, T = 16, 512
     h = Tensor(t.idx, t.vals, t.dims).build(mode, "mttkrp", threadlen=L, tile_nnz=T, host_only=True,
-                                             xcd_blocks=8)
+                                             xcd_blocks=8, xcd_mode=xmode)
     info = h.info(mode)
     assert info["xcd_blocks"] == 8
     pm = [m for m in range(len(dims)) if m != mode]
     bm = info["block_mode"]
-    assert bm == max(pm, key=lambda m: (dims[m], -m))
+    assert bm == (xmode if xmode >= 0 else max(pm, key=lambda m: (dims[m], -m)))
     blk = _blocks_of(t, bm)[np.asarray(t.idx[bm])]
     perm, heads, rows = [], [], []
     for b in range(8):
@@ -242,6 +244,9 @@ def test_xcd_blocks_refusals():
     assert e.value.code == _lib.FCOO_EINVAL
     with pytest.raises(FcooError) as e:
         h.build(0, "mttkrp", host_only=True, xcd_blocks=4)
+    assert e.value.code == _lib.FCOO_EINVAL
+    with pytest.raises(FcooError) as e:                           # the index mode is no product mode
+        h.build(0, "mttkrp", host_only=True, xcd_blocks=8, xcd_mode=0)
     assert e.value.code == _lib.FCOO_EINVAL
 
 
