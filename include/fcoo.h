@@ -196,6 +196,30 @@ int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const *factors, 
 int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,
                   float *M, void *stream);
 
+/* Bytes of the fixed device scratch array behind fcoo_spmttkrp_noalloc. */
+#define FCOO_NOALLOC_SCRATCH_BYTES (16ll << 20)
+
+/*
+ * fcoo_spmttkrp_noalloc -- fcoo_spmttkrp for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, kernels and result (bitwise equal
+ * to fcoo_spmttkrp on the same build and inputs), but the call allocates
+ * nothing: its scratch -- the tile carries, 2 x ntiles x R floats (rounded up
+ * to 256 bytes), plus xcd_blocks x dims[mode] x R floats of partial rows for
+ * an XCD-blocked build -- lives in one library-owned device array of
+ * FCOO_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * (which looks its address up with the GPU current) until the process ends.
+ * The caller still owns and passes factors and M.  Every scratch element the
+ * call reads it first writes, so nothing needs clearing between calls.
+ * All calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the
+ * caller.
+ * Errors: as fcoo_spmttkrp; FCOO_ERANGE when the scratch needed exceeds
+ * FCOO_NOALLOC_SCRATCH_BYTES (nothing is launched).
+ */
+int fcoo_spmttkrp_noalloc(fcoo_tensor *t, int mode, const void *const *factors, int dtype, int R,
+                          float *M, void *stream);
+
 /*
  * fcoo_spttm -- Y = X x_mode U (Eq. 3), semi-sparse result:
  *   Y[g, :] = sum over nonzeros e of fibre g of val(e) * U[i_mode(e), :]

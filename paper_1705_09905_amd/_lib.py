@@ -74,6 +74,7 @@ _SIGS = {
     "fcoo_info": (_i, [_vp, _i, _i, C.POINTER(fcoo_info_t)]),
     "fcoo_export": (_i, [_vp, _i, _i, C.POINTER(_vp), _vp, _vp, _vp, _vp, _vp, _vp]),
     "fcoo_spmttkrp": (_i, [_vp, _i, C.POINTER(_vp), _i, _i, _vp, _vp]),
+    "fcoo_spmttkrp_noalloc": (_i, [_vp, _i, C.POINTER(_vp), _i, _i, _vp, _vp]),
     "fcoo_spttm": (_i, [_vp, _i, _vp, _i, _i, _vp, _vp]),
     "fcoo_spttmc": (_i, [_vp, _i, C.POINTER(_vp), _i, C.POINTER(_i), _vp, _vp]),
     "fcoo_spmttkrp_values": (_i, [_vp, _i, _vp, C.POINTER(_vp), _i, _i, _vp, _vp]),

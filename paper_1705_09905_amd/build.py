@@ -30,6 +30,7 @@ SOURCES = [
     "fcoo_devbuild.hip",
     "fcoo_ops.hip",
     "fcoo_cp.hip",
+    "fcoo_noalloc.hip",
     "seg_f32.hip",
     "seg_bf16.hip",
     "seg_bf16_half.hip",

@@ -494,7 +494,7 @@ static int build_device(Built &b, hipStream_t s)
 // The build of (op, mode), or NULL with *rc set: FCOO_EINVAL for a null
 // handle, a mode outside [0, order) or an unknown op; FCOO_ENOTBUILT when
 // that (op, mode) has no build (on the device, if need_device).
-static Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device, int *rc)
+Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device, int *rc)
 {
     if (!t) { *rc = fail(FCOO_EINVAL, "null handle"); return nullptr; }
     if (mode < 0 || mode >= t->order) { *rc = fail(FCOO_EINVAL, "mode %d out of range", mode); return nullptr; }

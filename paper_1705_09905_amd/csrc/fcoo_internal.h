@@ -139,6 +139,9 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, i
 // b.pmodes, b.tile_nnz
 int setup_blocks(const fcoo_tensor *t, Built &b, int nblk, int xmode);
 int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
+// the build of (op, mode), or NULL with *rc set (FCOO_EINVAL: null handle, mode
+// or op out of range; FCOO_ENOTBUILT: no build, or none on the device if need_device)
+Built *get_built(fcoo_tensor *t, int mode, int op, bool need_device, int *rc);
 
 // launchers implemented in the .hip files (return FCOO_OK or an error code)
 struct TileProblem {
