@@ -58,8 +58,10 @@ def kernel_hash() -> str:
 
 
 def op_bytes(op, Z, N, R, nseg, In, P, sf=4):
-    """Algorithmic bytes of one SpMTTKRP / SpTTM on one mode."""
-    flags = (Z + 7) // 8 + 4 * ((P + 31) // 32)
+    """Algorithmic bytes of one SpMTTKRP / SpTTM on one mode.  Of the flags
+    only bf is counted: the kernels derive the heads before each run from bf
+    popcounts and read no sf word (P is kept for the record)."""
+    flags = (Z + 7) // 8
     if op == "mttkrp":
         return 4 * Z * (N - 1) + 4 * Z + flags + 4 * nseg + Z * (N - 1) * R * sf + 4 * In * R
     return 4 * Z + 4 * Z + flags + Z * R * sf + 4 * nseg * R
@@ -68,24 +70,32 @@ def op_bytes(op, Z, N, R, nseg, In, P, sf=4):
 def compulsory_bytes(op, Z, N, R, nseg, In, P, distinct, mode, sf=4):
     """Bytes one SpMTTKRP / SpTTM must move at the least: the streams and
     the output as in op_bytes, but each distinct factor row read once."""
-    flags = (Z + 7) // 8 + 4 * ((P + 31) // 32)
+    flags = (Z + 7) // 8
     if op == "mttkrp":
         rows = sum(distinct[k] for k in range(N) if k != mode)
         return 4 * Z * (N - 1) + 4 * Z + flags + 4 * nseg + rows * R * sf + 4 * In * R
     return 8 * Z + flags + distinct[mode] * R * sf + 4 * nseg * R
 
 
+def device_copy(torch, src, dst):
+    """The library's own plain copy kernel (fcoo_device_copy) on torch's stream."""
+    from paper_1705_09905_amd import _lib
+    _lib.check(_lib.fcoo_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                     src.numel() * src.element_size(),
+                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
-    """Device-to-device copy rate (read + write bytes / time) of a plain
-    1 GiB copy, for comparison with the kernels' traffic."""
+    """Device-to-device copy rate (read + write bytes / time) of the library's
+    plain copy kernel over 1 GiB, for comparison with the kernels' traffic."""
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    device_copy(torch, src, dst)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        dst.copy_(src)
+        device_copy(torch, src, dst)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -252,19 +262,23 @@ def cp_planted(args, log, cpu_rec):
         h.build(m, "mttkrp", threadlen=args.threadlen, tile_nnz=4096, device=True)
     torch.cuda.synchronize()
     build_s = time.time() - t0
-    layout = {}
-    Ft = [torch.tensor(a.astype(np.float32), device="cuda") for a in init]
-    for m in range(t.order):
-        # tile size and XCD layout per mode, chosen by timing SpMTTKRP (not timed below)
-        r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
-        layout[f"mode{m}"] = {"tile_nnz": r["tile_nnz"], "xcd_blocks": r["xcd_blocks"]}
-    del Ft
-    log(f"planted CP-ALS: built in {build_s:.2f}s, layout {layout}")
+    log(f"planted CP-ALS: built in {build_s:.2f}s")
     keep = (1, S) if cpu_rec is not None else ()
     rec = {"workload": f"{t.name}: CP-ALS, R = {R}, {S} sweeps", "dims": t.dims, "nnz": t.nnz, "R": R,
-           "sweeps": S, "layout": layout, "device_build_s": round(build_s, 3)}
+           "sweeps": S, "layout": {}, "device_build_s": round(build_s, 3)}
     kept = {}
     for dt in ("f32", "bf16"):
+        # tile size, XCD layout and lane chunk per mode, chosen by timing
+        # SpMTTKRP with this storage type's factors (not timed below)
+        Ft = [torch.tensor(a.astype(np.float32), device="cuda").to(
+            torch.float32 if dt == "f32" else torch.bfloat16).contiguous() for a in init]
+        layout = {}
+        for m in range(t.order):
+            r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
+            layout[f"mode{m}"] = {k: r[k] for k in ("tile_nnz", "xcd_blocks", "xcd_mode", "lane_cols")}
+        del Ft
+        rec["layout"][dt] = layout
+        log(f"planted CP-ALS {dt}: layout {layout}")
         fits, secs, kept[dt] = cp_gpu(h, t, R, S, init, dt, keep_after=keep)
         rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
                    "s_per_iter_min": round(float(np.min(secs)), 6),
@@ -348,19 +362,29 @@ def run_extra(args, log):
     N = t.order
     init = synth.factors(t.dims, R, cfg, role="init")
     layout = {}
-    if args.tile == 0:
-        # layout per mode (tile size, XCD blocks) chosen by timing SpMTTKRP;
-        # the fused residual kernel of gradient CP prefers other tile sizes
-        # than plain SpMTTKRP, so there only the XCD layout is chosen
-        import torch
-        Ft = [torch.tensor(a.astype(np.float32), device="cuda") for a in init]
+
+    def tune(dt):
+        # layout per mode (tile size, XCD blocks, lane chunk) chosen by timing
+        # SpMTTKRP with this storage type's factors; the fused residual kernel
+        # of gradient CP prefers other tile sizes than plain SpMTTKRP, so there
+        # only the XCD layout is chosen
+        if args.tile:
+            return
+        Ft = [torch.tensor(a.astype(np.float32), device="cuda").to(
+            torch.float32 if dt == "f32" else torch.bfloat16).contiguous() for a in init]
         cand = [2048, 4096, 8192] if kind == "cpals" else [4096]
+        lay = {}
         for m in range(N):
             r = h.autotune(m, "mttkrp", Ft, tiles=cand)
-            layout[f"mode{m}"] = {"tile_nnz": r["tile_nnz"], "xcd_blocks": r["xcd_blocks"]}
-        del Ft
-        log(f"autotuned layout {layout}")
-    infos = [h.info(m) for m in range(t.order)]
+            lay[f"mode{m}"] = {k: r[k] for k in ("tile_nnz", "xcd_blocks", "xcd_mode", "lane_cols")}
+        layout[dt] = lay
+        log(f"autotuned layout {dt}: {lay}")
+
+    if kind != "cpals":
+        tune("f32")
+    # slices (non-empty rows) per mode: the segments of the plain layout, which
+    # the byte model counts whatever layout the autotuner keeps
+    nslices = [int(np.count_nonzero(np.bincount(t.idx[m], minlength=t.dims[m]))) for m in range(N)]
     rec = {"metric": METRIC, "n_gpus": 1, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic", "build_s": round(build_s, 2),
            "config": {"workload": f"{t.name}: " + ("CP-ALS" if kind == "cpals" else "gradient CP (MSE, Adam)")
@@ -370,7 +394,7 @@ def run_extra(args, log):
     def mttkrp_bytes(sf, own=False):
         b = 0
         for m in range(N):
-            b += op_bytes("mttkrp", t.nnz, N, R, infos[m]["nseg"], t.dims[m], infos[m]["npart"], sf)
+            b += op_bytes("mttkrp", t.nnz, N, R, nslices[m], t.dims[m], -(-t.nnz // args.threadlen), sf)
             if own:
                 b += t.dims[m] * R * sf
         return b
@@ -379,6 +403,7 @@ def run_extra(args, log):
         sweeps = args.cp_sweeps
         rec["sweeps"] = sweeps
         for dt in ("f32", "bf16"):
+            tune(dt)
             fits, secs, _ = cp_gpu(h, t, R, sweeps, init, dt)
             s_it = float(np.median(secs[1:] if len(secs) > 1 else secs))
             B = mttkrp_bytes(4 if dt == "f32" else 2)
@@ -474,7 +499,7 @@ def main():
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        device_copy(torch, src, dst)
         torch.cuda.synchronize()
         del src, dst
     Rs = [int(r) for r in args.ranks.split(",")]
@@ -500,7 +525,8 @@ def main():
         for m in range(t.order):
             for op in ("mttkrp", "ttm"):
                 r = h.autotune(m, op, facs[max(Rs)], tiles=[2048, 4096, 8192])
-                tiles[f"{op}{m}"] = r["tile_nnz"] if r["xcd_blocks"] <= 1 else f"{r['tile_nnz']}/xcd{r['xcd_blocks']}"
+                tiles[f"{op}{m}"] = (r["tile_nnz"] if r["xcd_blocks"] <= 1
+                                     else f"{r['tile_nnz']}/xcd{r['xcd_blocks']}-by-mode{r['xcd_mode']}")
         log(f"autotuned tile sizes {tiles} in {time.time() - t0:.1f}s")
     # the same builds sorted and encoded on the GPU (identical arrays): timed for the record
     torch.cuda.synchronize()
@@ -509,11 +535,15 @@ def main():
         for op in ("mttkrp", "ttm"):
             inf = h.info(m, op)
             h.build(m, op, threadlen=args.threadlen, tile_nnz=inf["tile_nnz"], device=True,
-                    xcd_blocks=inf["xcd_blocks"])
+                    xcd_blocks=inf["xcd_blocks"], xcd_mode=inf["block_mode"], lane_cols=inf["lane_cols"])
     torch.cuda.synchronize()
     dev_build_s = time.time() - t0
     log(f"F-COO built on the GPU (6 builds) in {dev_build_s:.2f}s")
     infos = {(op, m): h.info(m, op) for m in range(t.order) for op in ("mttkrp", "ttm")}
+    # segments of the method: slices (non-empty rows) for SpMTTKRP, whatever
+    # layout the autotuner kept (an XCD-blocked build splits them), fibres for SpTTM
+    nsegs = {(op, m): (int(np.count_nonzero(np.bincount(t.idx[m], minlength=t.dims[m]))) if op == "mttkrp"
+                       else infos[(op, m)]["nseg"]) for (op, m) in infos}
     outs = {}
     for R in Rs:
         for m in range(t.order):
@@ -563,7 +593,7 @@ def main():
     detail = []
     for (op, m, R) in launches:
         inf = infos[(op, m)]
-        B = op_bytes(op, t.nnz, N, R, inf["nseg"], t.dims[m], inf["npart"])
+        B = op_bytes(op, t.nnz, N, R, nsegs[(op, m)], t.dims[m], inf["npart"])
         F = op_flops(op, t.nnz, N, R)
         step_bytes += B
         step_flops += F
@@ -623,7 +653,7 @@ def main():
     # the least bytes of the dominant kernel (each distinct factor row once),
     # and a plain device copy's rate on this GPU
     distinct = [int(np.count_nonzero(np.bincount(t.idx[k], minlength=t.dims[k]))) for k in range(t.order)]
-    comp = [compulsory_bytes(op, t.nnz, N, R, infos[(op, m)]["nseg"], t.dims[m], infos[(op, m)]["npart"],
+    comp = [compulsory_bytes(op, t.nnz, N, R, nsegs[(op, m)], t.dims[m], infos[(op, m)]["npart"],
                              distinct, m) for (op, m, R) in launches if (op, R) == dom]
     roofline["compulsory_bytes_per_launch"] = int(np.mean(comp))
     roofline["compulsory_GBps"] = round(np.mean(comp) / (avg_ms / 1e3) / 1e9, 1)
@@ -691,8 +721,8 @@ def main():
         kb = {}
         for m in range(N):
             inf = infos[("mttkrp", m)]
-            flags = (t.nnz + 7) // 8 + 4 * ((inf["npart"] + 31) // 32)
-            kb[m] = (4 * t.nnz * N + flags + 4 * inf["nseg"] + t.nnz * (N - 1) * Rk * 4
+            flags = (t.nnz + 7) // 8
+            kb[m] = (4 * t.nnz * N + flags + 4 * nsegs[("mttkrp", m)] + t.nnz * (N - 1) * Rk * 4
                      + 4 * t.dims[m] * W)
         out["spttmc"] = {"R_per_mode": Rk, "width": W,
                          "tile_ms_per_mode": [round(km[m], 4) for m in range(N)],

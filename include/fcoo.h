@@ -84,6 +84,23 @@ typedef struct {
                         ranges define the blocks (FCOO_EINVAL if it is not a
                         product mode of the build); 0: the product mode with
                         the most rows. */
+    int lane_cols;   /* bfloat16 factors, SpMTTKRP / SpTTM: columns of a row
+                        that one lane reads per gather, 4 (8-byte pieces; the
+                        kernel then runs 4 waves per SIMD) or 8 (16-byte
+                        pieces, 3 waves per SIMD; always so with R > 64 or R
+                        not a multiple of 4, with the fused residual and with
+                        SpTTMc).  0: 4 with exactly two product modes and R <=
+                        64, else 8.  fcoo_autotune times both. */
+    int single_pass; /* 1: finish the segments that cross tile boundaries inside
+                        the tile kernel (the paper's adjacent synchronization,
+                        Sec. IV-D): each tile publishes its two boundary
+                        partials tagged with the launch, and the tile holding
+                        a segment's closing head waits (bounded) for its
+                        chain's partials and writes the row, so no fix-up pass
+                        runs.  Workgroups take tiles in start order from a
+                        ticket counter.  Plain layout only (FCOO_EINVAL with
+                        xcd_blocks); fcoo_spmttkrp_noalloc keeps the fix-up
+                        pass.  0: fix-up pass (default). */
 } fcoo_opts;
 
 /* Sizes of one built (op, mode). */
@@ -102,6 +119,11 @@ typedef struct {
     int32_t on_device;    /* 1 if uploaded                                        */
     int32_t xcd_blocks;   /* 1, or the number of XCD blocks (SpMTTKRP)           */
     int32_t block_mode;   /* mode whose index ranges define the blocks, or -1    */
+    int32_t lane_cols;    /* fcoo_opts.lane_cols of the build (0: default rule)  */
+    int32_t single_pass;  /* 1 if built with fcoo_opts.single_pass              */
+    int32_t sp_gave_up;   /* single pass: 1 if a wait for another tile's partial
+                             gave up (its result is then wrong); fcoo_info
+                             waits for the device to read it                    */
 } fcoo_info_t;
 
 /*
@@ -159,12 +181,14 @@ int fcoo_export(const fcoo_tensor *t, int mode, int op, int32_t *const *pidx, fl
 
 /*
  * fcoo_autotune -- choose the layout of one (op, mode) by timing: each
- * candidate tile_nnz, and for op = MTTKRP each with xcd_blocks 0 and 8, is
- * built (on the GPU when the sort key fits 64 bits, else on the host; the
- * current threadlen is kept, default 16) and its operation run once to warm
- * up, then `reps` times between two HIP events on `stream`; the fastest
- * build is left in place (the paper tunes its launch shape per dataset,
- * Sec. V, Table V).
+ * candidate tile_nnz -- for op = MTTKRP each with xcd_blocks 0 and with
+ * xcd_blocks 8 split by every product mode (xcd_mode), skipping blocked
+ * layouts the build refuses -- is built (on the GPU when the sort key fits 64
+ * bits, else on the host; the current threadlen is kept, default 16), and for
+ * bfloat16 factors with R <= 64 a multiple of 4 both lane_cols 4 and 8 are
+ * tried on it; each is run once to warm up, then `reps` times between two
+ * HIP events on `stream`, and the fastest is left in place (the paper tunes
+ * its launch shape per dataset, Sec. V, Table V).
  *   factors  as fcoo_spmttkrp (op = MTTKRP) or factors[mode] = U (op = TTM);
  *            device data of `dtype`, R columns.
  *   tiles    host array of `ncand` candidate tile sizes (each a multiple of
@@ -324,6 +348,17 @@ int fcoo_cp_als_iter(fcoo_tensor *t, void *const *factors, int dtype, int R, dou
  * across blocks.  Errors: FCOO_EINVAL, FCOO_EUNSUPPORTED, FCOO_EHIP, FCOO_ENOMEM.
  */
 int fcoo_gram(fcoo_tensor *t, int mode, const void *A, int dtype, int R, double *G, void *stream);
+
+/*
+ * fcoo_device_copy -- copy `bytes` of device memory from src to dst with the
+ * library's own plain copy kernel (16-byte loads and stores): the device-copy
+ * bandwidth the sparse kernels are measured against, and a kernel of known
+ * traffic for calibrating hardware byte counters.  Not part of the method.
+ *   src, dst  device, 16-byte aligned, not overlapping (caller-owned).
+ *   bytes     a non-negative multiple of 16.
+ * Errors: FCOO_EINVAL (null pointer, misalignment, size), FCOO_EHIP.
+ */
+int fcoo_device_copy(const void *src, void *dst, int64_t bytes, void *stream);
 
 /*
  * fcoo_set_tile_events -- instrumentation for callers that time the tile

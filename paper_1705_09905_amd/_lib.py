@@ -35,7 +35,8 @@ ERROR_NAMES = {
 
 class fcoo_opts(C.Structure):
     _fields_ = [("threadlen", C.c_int), ("tile_nnz", C.c_int), ("host_only", C.c_int),
-                ("device", C.c_int), ("xcd_blocks", C.c_int), ("xcd_mode", C.c_int)]
+                ("device", C.c_int), ("xcd_blocks", C.c_int), ("xcd_mode", C.c_int),
+                ("lane_cols", C.c_int), ("single_pass", C.c_int)]
 
 
 class fcoo_info_t(C.Structure):
@@ -43,7 +44,8 @@ class fcoo_info_t(C.Structure):
                 ("ntiles", C.c_int64), ("nfix", C.c_int64), ("nempty", C.c_int64),
                 ("bytes_format", C.c_int64), ("bytes_device", C.c_int64),
                 ("threadlen", C.c_int32), ("tile_nnz", C.c_int32), ("order", C.c_int32),
-                ("on_device", C.c_int32), ("xcd_blocks", C.c_int32), ("block_mode", C.c_int32)]
+                ("on_device", C.c_int32), ("xcd_blocks", C.c_int32), ("block_mode", C.c_int32),
+                ("lane_cols", C.c_int32), ("single_pass", C.c_int32), ("sp_gave_up", C.c_int32)]
 
 
 class FcooError(RuntimeError):
@@ -83,6 +85,7 @@ _SIGS = {
     "fcoo_cp_als_iter": (_i, [_vp, C.POINTER(_vp), _i, _i, _vp, _vp, _i, _vp, _vp, _vp]),
     "fcoo_gram": (_i, [_vp, _i, _vp, _i, _i, _vp, _vp]),
     "fcoo_set_tile_events": (_i, [_vp, _vp, _vp]),
+    "fcoo_device_copy": (_i, [_vp, _vp, _i64, _vp]),
     "fcoo_autotune": (_i, [_vp, _i, _i, C.POINTER(_vp), _i, _i, _vp, _i, _i, C.POINTER(fcoo_opts),
                            C.POINTER(C.c_float), _vp]),
     "fcoo_destroy": (None, [_vp]),

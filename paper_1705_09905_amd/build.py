@@ -31,6 +31,7 @@ SOURCES = [
     "fcoo_ops.hip",
     "fcoo_cp.hip",
     "fcoo_noalloc.hip",
+    "fcoo_copy.hip",
     "seg_f32.hip",
     "seg_bf16.hip",
     "seg_bf16_half.hip",

@@ -131,12 +131,12 @@ void Built::free_device()
     bpart_cap = 0;
     for (auto &p : d_pidx) { if (p) (void)hipFree(p); p = nullptr; }
     void *ptrs[] = {d_val, d_bf, d_sf, d_seg_row, d_tile_seg0, d_perm, d_fix, d_empty, d_carry,
-                    d_gperm, d_partial};
+                    d_gperm, d_partial, d_sp_from, d_sp_words, d_sp_ticket, d_sp_err};
     for (void *p : ptrs) if (p) (void)hipFree(p);
     d_val = nullptr; d_bf = nullptr; d_sf = nullptr; d_seg_row = nullptr; d_tile_seg0 = nullptr;
     d_perm = nullptr; d_fix = nullptr; d_empty = nullptr; d_carry = nullptr; d_gperm = nullptr;
-    d_partial = nullptr;
-    carry_cap = 0; partial_cap = 0; device_bytes = 0;
+    d_partial = nullptr; d_sp_from = nullptr; d_sp_words = nullptr; d_sp_ticket = nullptr; d_sp_err = nullptr;
+    carry_cap = 0; partial_cap = 0; device_bytes = 0; sp_words_cap = 0; sp_tickets = 0; sp_epoch = 0;
     on_device = false;
 }
 
@@ -268,6 +268,54 @@ int setup_blocks(const fcoo_tensor *t, Built &b, int nblk, int xmode)
     b.blk_ts[nblk] = ntiles;
     b.nblk = nblk;
     b.bmode = bm;
+    return FCOO_OK;
+}
+
+int setup_single_pass(Built &b, hipStream_t s)
+{
+    if (b.nblk > 1) return fail(FCOO_EINVAL, "single_pass needs the plain layout (no xcd_blocks)");
+    if (b.ntiles > (int64_t)0x7fffffff) return fail(FCOO_EUNSUPPORTED, "single_pass: too many tiles");
+    std::vector<int32_t> from(b.ntiles + 1, -1);
+    b.sp_tail_from = -1;
+    for (int64_t e = 0; e < b.nfix(); ++e) {
+        const int32_t tb = b.fix[3 * e], ta = b.fix[3 * e + 1];
+        if (tb < b.ntiles) from[tb] = ta;
+        else b.sp_tail_from = ta;
+    }
+    int64_t acct = 0;
+    int rc = upload_i32(&b.d_sp_from, from, 0, s, &acct);
+    if (rc) return rc;
+    FCOO_HIP(hipMalloc((void **)&b.d_sp_ticket, sizeof(unsigned long long)));
+    FCOO_HIP(hipMalloc((void **)&b.d_sp_err, sizeof(int)));
+    FCOO_HIP(hipMemsetAsync(b.d_sp_ticket, 0, sizeof(unsigned long long), s));
+    FCOO_HIP(hipMemsetAsync(b.d_sp_err, 0, sizeof(int), s));
+    FCOO_HIP(hipStreamSynchronize(s));
+    b.device_bytes += acct + (int64_t)sizeof(unsigned long long) + (int64_t)sizeof(int);
+    b.sp_tickets = 0;
+    b.sp_epoch = 0;
+    b.sp = true;
+    return FCOO_OK;
+}
+
+int prep_single_pass(Built *b, TileProblem &p, hipStream_t s)
+{
+    if (!b->sp || b->nnz == 0) return FCOO_OK;
+    const int64_t need = 2 * b->ntiles * (int64_t)p.R;
+    if (need > b->sp_words_cap) {
+        // fresh words hold tag 0, which no launch uses
+        if (b->d_sp_words) {
+            FCOO_HIP(hipStreamSynchronize(s));
+            FCOO_HIP(hipFree(b->d_sp_words));
+            b->d_sp_words = nullptr;
+            b->sp_words_cap = 0;
+        }
+        FCOO_HIP(hipMalloc((void **)&b->d_sp_words, (size_t)need * sizeof(uint64_t)));
+        FCOO_HIP(hipMemsetAsync(b->d_sp_words, 0, (size_t)need * sizeof(uint64_t), s));
+        b->sp_words_cap = need;
+    }
+    if (++b->sp_epoch == 0) b->sp_epoch = 1;
+    p.sp_words = b->d_sp_words;
+    p.sp_epoch = b->sp_epoch;
     return FCOO_OK;
 }
 
@@ -477,7 +525,8 @@ static int build_device(Built &b, hipStream_t s)
         if ((rc = upload(&b.d_bf, w.data(), words, 2, s, &acct))) return rc;
         FCOO_HIP(hipStreamSynchronize(s));
     }
-    if ((rc = upload(&b.d_sf, b.sf.data(), (int64_t)b.sf.size(), 1, s, &acct))) return rc;
+    // sf stays on the host (exported with the format): the kernels count the
+    // segment heads before each run from bf popcounts, so no device work reads it
     if (b.op == FCOO_OP_MTTKRP)
         if ((rc = upload(&b.d_seg_row, b.seg.data(), b.nseg, 1, s, &acct))) return rc;
     if ((rc = upload(&b.d_tile_seg0, b.tile_seg0.data(), b.ntiles, 1, s, &acct))) return rc;
@@ -579,7 +628,11 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
     const bool on_gpu = opts && opts->device;
     const int nblk = opts ? opts->xcd_blocks : 0;
     const int xmode = opts ? opts->xcd_mode - 1 : -1;
+    const int lane_cols = opts ? opts->lane_cols : 0;
+    const bool single_pass = opts && opts->single_pass;
     if (host_only && on_gpu) return fail(FCOO_EINVAL, "host_only and device are exclusive");
+    if (lane_cols != 0 && lane_cols != 4 && lane_cols != 8)
+        return fail(FCOO_EINVAL, "lane_cols %d not in {0, 4, 8}", lane_cols);
     if (threadlen != 8 && threadlen != 16 && threadlen != 32 && threadlen != 64)
         return fail(FCOO_EINVAL, "threadlen %d not in {8, 16, 32, 64}", threadlen);
     if (tile_nnz <= 0 || tile_nnz % 256 || tile_nnz % threadlen || tile_nnz > (1 << 20))
@@ -594,10 +647,12 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
         } catch (const std::bad_alloc &) {
             rc = fail(FCOO_ENOMEM, "device build (host side)");
         }
+        if (!rc && single_pass) rc = setup_single_pass(b, (hipStream_t)stream);
         if (rc) {
             b.free_device();
             b = Built();
         }
+        b.lane_cols = lane_cols;
         return rc;
     }
     try {
@@ -607,8 +662,10 @@ int fcoo_build(fcoo_tensor *t, int mode, int op, const fcoo_opts *opts, void *st
         return fail(FCOO_ENOMEM, "host build");
     }
     if (rc) return rc;
+    b.lane_cols = lane_cols;
     if (host_only) return FCOO_OK;
     rc = build_device(b, (hipStream_t)stream);
+    if (!rc && single_pass) rc = setup_single_pass(b, (hipStream_t)stream);
     if (rc) { b.free_device(); return rc; }
     return FCOO_OK;
 }
@@ -634,6 +691,15 @@ int fcoo_info(const fcoo_tensor *t, int mode, int op, fcoo_info_t *info)
     info->on_device = b->on_device ? 1 : 0;
     info->xcd_blocks = b->nblk;
     info->block_mode = b->bmode;
+    info->lane_cols = b->lane_cols;
+    info->single_pass = b->sp ? 1 : 0;
+    info->sp_gave_up = 0;
+    if (b->sp && b->d_sp_err) {
+        // reads the flag a bounded wait of the single-pass kernel sets (synchronous)
+        int e = 0;
+        FCOO_HIP(hipMemcpy(&e, b->d_sp_err, sizeof(int), hipMemcpyDeviceToHost));
+        info->sp_gave_up = e != 0;
+    }
     return FCOO_OK;
 }
 
@@ -718,6 +784,7 @@ int fcoo_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, int dtyp
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
+    if ((rc = prep_single_pass(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -758,6 +825,7 @@ int fcoo_spttmc(fcoo_tensor *t, int mode, const void *const *factors, int dtype,
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * W, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
+    if ((rc = prep_single_pass(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -783,6 +851,7 @@ int fcoo_spttm(fcoo_tensor *t, int mode, const void *U, int dtype, int R, float 
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
+    if ((rc = prep_single_pass(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -814,6 +883,7 @@ int fcoo_spmttkrp_values(fcoo_tensor *t, int mode, const float *g, const void *c
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
+    if ((rc = prep_single_pass(b, p, s))) return rc;
     p.ev_before = t->ev_before;
     p.ev_after = t->ev_after;
     return launch_segmented(p, s, false);
@@ -842,6 +912,7 @@ int fcoo_resid_spmttkrp(fcoo_tensor *t, int mode, const void *const *factors, in
     if ((rc = ensure_device_floats(&b->d_carry, &b->carry_cap, 2 * b->ntiles * (int64_t)R, s))) return rc;
     p.carry = b->d_carry;
     if ((rc = prep_blocks(b, p, s))) return rc;
+    if ((rc = prep_single_pass(b, p, s))) return rc;
     if (loss) {
         if ((rc = ensure_device_doubles(&b->d_partial, &b->partial_cap, b->ntiles + 1, s))) return rc;
         p.partial = b->d_partial;

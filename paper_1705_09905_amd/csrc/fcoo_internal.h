@@ -34,6 +34,7 @@ struct Built {
     bool on_device = false;
     bool host_arrays = true;                  // false: built on the GPU, per-nonzero arrays on the device only
     int op = 0, mode = 0, threadlen = 0, tile_nnz = 0;
+    int lane_cols = 0;                        // bfloat16 columns per lane chunk (4, 8; 0: default rule)
     int64_t nnz = 0, nseg = 0, npart = 0, ntiles = 0;
     std::vector<int> imodes, pmodes;
 
@@ -64,7 +65,7 @@ struct Built {
     int32_t *d_pidx[kMaxOrder] = {};
     float *d_val = nullptr;
     uint32_t *d_bf = nullptr;                 // bit stream as uint32 words, +2 zero words
-    uint32_t *d_sf = nullptr;
+    uint32_t *d_sf = nullptr;                 // device builds only (where it is made), for export
     int32_t *d_seg_row = nullptr;             // MTTKRP only
     int32_t *d_tile_seg0 = nullptr;
     int32_t *d_perm = nullptr;
@@ -80,6 +81,18 @@ struct Built {
     int64_t bpart_cap = 0;                    // floats
     double *d_partial = nullptr;              // per-tile float64 partial sums
     int64_t partial_cap = 0;
+
+    // single pass (fcoo_opts.single_pass): segments crossing tiles are finished
+    // inside the tile kernel from published boundary partials, no fix-up pass
+    bool sp = false;
+    int32_t *d_sp_from = nullptr;             // ntiles: chain start tile of each tile's first head, or -1
+    int sp_tail_from = -1;                    // chain start of the segment open at the end
+    uint64_t *d_sp_words = nullptr;           // ntiles x 2 x R published partials
+    int64_t sp_words_cap = 0;                 // words
+    unsigned long long *d_sp_ticket = nullptr;   // ticket counter (never reset)
+    int *d_sp_err = nullptr;                  // set by a wait that gave up
+    unsigned long long sp_tickets = 0;        // tickets taken by earlier launches
+    uint32_t sp_epoch = 0;                    // tag of the last launch
 
     int64_t nfix() const { return (int64_t)fix.size() / 3; }
     int64_t max_block_tiles() const;
@@ -138,6 +151,8 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, i
 // mode xmode (-1: the product mode with the most rows); needs b.op, b.mode,
 // b.pmodes, b.tile_nnz
 int setup_blocks(const fcoo_tensor *t, Built &b, int nblk, int xmode);
+// the single-pass chain table of a finished build (fix list -> per-tile chain starts) and its counters
+int setup_single_pass(Built &b, hipStream_t s);
 int check_factors(const fcoo_tensor *t, int skip_mode, const void *const *factors, int dtype, int R);
 // the build of (op, mode), or NULL with *rc set (FCOO_EINVAL: null handle, mode
 // or op out of range; FCOO_ENOTBUILT: no build, or none on the device if need_device)
@@ -162,7 +177,12 @@ struct TileProblem {
     // SpTTMc: Kronecker rows; R is then the output width prod kr[q]
     bool kron = false;
     int kr[kMaxOrder] = {};          // per product mode q: columns of its factor
+    // single pass (set by prep_single_pass; sp_words null: carries + fix-up)
+    uint64_t *sp_words = nullptr;
+    uint32_t sp_epoch = 0;
 };
+// single-pass words of a build for a launch of width R (no-op for other builds)
+int prep_single_pass(Built *b, TileProblem &p, hipStream_t s);
 int launch_segmented(const TileProblem &p, hipStream_t s, bool resid);
 int launch_permute_values(const Built &b, const float *g, float *out, hipStream_t s);
 int launch_reduce_partials(const double *partial, int64_t n, double scale, double *out, hipStream_t s);

@@ -206,10 +206,13 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         a.tile_nnz = b.tile_nnz;
         a.nseg = (int)b.nseg;
         a.inv_nnz = p.inv_nnz;
-        // bfloat16 SpMTTKRP with two product modes and R <= 64: 4-column (8-byte)
-        // lane chunks, which hold twice the rows per gather batch (with three
-        // or more, the batch per mode gets too short and 8-column chunks win)
-        L.half = p.dtype == FCOO_BF16 && !resid && !p.kron && np == 2 && R % 4 == 0 && R <= 64;
+        // bfloat16 in 4-column (8-byte) lane chunks: twice the rows per gather
+        // batch at 4 waves per SIMD, against 8-column chunks at 3 waves.  The
+        // build's lane_cols picks (fcoo_autotune times both); by default 4
+        // columns with exactly two product modes (with three, the batch per mode
+        // gets short and 8-column chunks won on the order-4 Zipf tensor)
+        const bool half_ok = p.dtype == FCOO_BF16 && !resid && !p.kron && np <= 3 && R % 4 == 0 && R <= 64;
+        L.half = half_ok && (b.lane_cols == 4 || (b.lane_cols == 0 && np == 2 && b.op == FCOO_OP_MTTKRP));
         const int V = (p.dtype == FCOO_F32 || L.half) ? 4 : 8;
         // a lane's VW columns must lie in one row piece of the (last) factor
         L.vec = ((p.kron ? p.kr[np - 1] : R) % V) == 0;
@@ -237,6 +240,15 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         L.rowmap = b.op == FCOO_OP_MTTKRP;
         a.nblk = b.nblk;
         a.rows_own = (int)b.rows;
+        if (p.sp_words) {
+            a.sp_words = p.sp_words;
+            a.sp_from = b.d_sp_from;
+            a.sp_ticket = b.d_sp_ticket;
+            a.sp_err = b.d_sp_err;
+            a.sp_base = b.sp_tickets;
+            a.sp_epoch = p.sp_epoch;
+            a.sp_tail_from = b.sp_tail_from;
+        }
         int64_t gx = b.ntiles;
         if (b.nblk > 1) {
             for (int k = 0; k <= b.nblk; ++k) a.blk_ts[k] = b.blk_ts[k];
@@ -251,8 +263,10 @@ int launch_segmented(const TileProblem &p, hipStream_t s, bool resid)
         else if (L.half) e = seg_launch_bf16_half(L, s);
         else e = resid ? seg_launch_bf16_resid(L, s) : seg_launch_bf16(L, s);
         if (e != hipSuccess) return hip_fail(e, "tile kernel launch");
+        if (p.sp_words)   // every workgroup of the launch takes one ticket
+            const_cast<Built &>(b).sp_tickets += (unsigned long long)L.grid.x * L.grid.y;
         if (p.ev_after) FCOO_HIP(hipEventRecord(p.ev_after, s));
-        const int64_t nfix = b.nfix();
+        const int64_t nfix = p.sp_words ? 0 : b.nfix();
         if (nfix > 0) {
             hipLaunchKernelGGL(dev::fixup_kernel, dim3((unsigned)nfix), dim3(256), 0, s, b.d_fix,
                                a.carry_a, a.carry_b, b.ntiles, R, a.out);

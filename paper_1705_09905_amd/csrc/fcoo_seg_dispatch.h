@@ -15,7 +15,7 @@ struct SegLaunch {
     int npt;         // product modes as a template value: 1, 2, 3, or 0 (runtime count)
     bool rowmap;     // output row = seg_row[segment] (SpMTTKRP) or the segment ordinal (SpTTM)
     int kb;          // SpTTMc: column blocks per lane (1, or KronBlock<FT>::KB)
-    bool half;       // bfloat16 SpMTTKRP in 4-column (8-byte) lane chunks
+    bool half;       // bfloat16 in 4-column (8-byte) lane chunks
     dim3 grid;
 };
 
@@ -69,12 +69,17 @@ static hipError_t seg_dispatch(const SegLaunch &L, hipStream_t s)
     }
 }
 
-// bfloat16 SpMTTKRP (two product modes) in 4-column lane chunks:
-// half the row bytes per lane, so twice the rows per gather batch.
+// bfloat16 in 4-column lane chunks (SpMTTKRP with 1-3 product modes, or
+// SpTTM): half the row bytes per lane, so twice the rows per gather batch.
 template <typename FT, int LPN>
 static hipError_t seg_np_half(const SegLaunch &L, hipStream_t s)
 {
-    return seg_go<FT, 4, LPN, 2, false, true>(L, s);
+    if (!L.rowmap) return seg_go<FT, 4, LPN, 1, false, false>(L, s);
+    switch (L.npt) {
+        case 1: return seg_go<FT, 4, LPN, 1, false, true>(L, s);
+        case 2: return seg_go<FT, 4, LPN, 2, false, true>(L, s);
+        default: return seg_go<FT, 4, LPN, 3, false, true>(L, s);
+    }
 }
 
 template <typename FT>

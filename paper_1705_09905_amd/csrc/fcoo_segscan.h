@@ -73,7 +73,49 @@ struct SegArgs {
     int64_t blk_ts[kXcdBlocks + 1];
     int nblk;                        // 1: plain tile order
     int rows_own;                    // RESID with blocks: rows of the index mode
+    // single pass (plain tile order): segments that cross tiles are finished
+    // inside this launch.  Each tile publishes its two boundary partials as
+    // words (float bits | epoch << 32); the tile holding a segment's closing
+    // head (or the last tile, for the segment open at the end) waits for the
+    // words of the chain's earlier tiles and writes the row.  Workgroups take
+    // their tile from a ticket counter, so every tile waited on has started.
+    uint64_t *sp_words;              // null: carries + fix-up pass; else ntiles x 2 x R words
+    const int32_t *sp_from;          // per tile: start tile of the chain its first head closes, or -1
+    unsigned long long *sp_ticket;   // ticket counter (never reset; sp_base is this launch's first)
+    int *sp_err;                     // the tag of the last launch whose bounded wait gave up (0: none)
+    unsigned long long sp_base;
+    uint32_t sp_epoch;               // this launch's tag (never 0)
+    int sp_tail_from;                // start tile of the segment open at the end of the tensor
 };
+
+constexpr int kSpinMax = 1 << 20;    // polls of one word before a wait gives up
+
+// Publish a boundary partial of the single-pass variant.
+__device__ __forceinline__ void sp_put(uint64_t *p, float v, uint32_t epoch)
+{
+    const uint64_t w = ((uint64_t)epoch << 32) | (uint64_t)__float_as_uint(v);
+    __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (bounded) for a published partial of this launch and return it.  A
+// wait that gives up writes the launch's tag to the error word, and every
+// other wait of the launch returns soon after it sees it there, so a launch
+// whose partials never arrive still ends in about one wait's bound.
+__device__ __forceinline__ float sp_get(const uint64_t *p, uint32_t epoch, int *err)
+{
+    uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int it = 0; (uint32_t)(w >> 32) != epoch; ++it) {
+        if (it >= kSpinMax) {
+            __hip_atomic_store(err, (int)epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0.f;
+        }
+        if ((it & 63) == 63 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (int)epoch)
+            return 0.f;
+        __builtin_amdgcn_s_sleep(2);
+        w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return __uint_as_float((uint32_t)w);
+}
 
 template <int N, int I = 0, class F>
 __device__ __forceinline__ void static_for(F &&f)
@@ -290,8 +332,11 @@ void seg_tile_kernel(SegArgs A)
     constexpr int RT = LPN * AW;                      // columns of this rank tile
 
     __shared__ int s_f[4];
-    __shared__ float s_a[4][RT];
-    __shared__ float s_b[4][RT];
+    // the four waves' boundary partials (a: rows 0-3, b: rows 4-7); the single
+    // pass reuses the rows for its chain sums once they have been read
+    __shared__ float s_ab[8][RT];
+    float (*s_a)[RT] = s_ab;
+    float (*s_b)[RT] = s_ab + 4;
     __shared__ double s_loss[4];
     __shared__ int s_hw[4];
 
@@ -299,7 +344,22 @@ void seg_tile_kernel(SegArgs A)
     const int lane = tid & 63, w = tid >> 6;
     const int q = lane / LPN, j = lane % LPN;
     int64_t tile = blockIdx.x;
-    if (A.nblk > 1) {
+    int ry = (int)blockIdx.y;                         // rank tile
+    if (A.sp_words) {
+        // single pass: tiles in the order workgroups start (tickets), so every
+        // tile this one may wait on is running or done
+        __shared__ unsigned long long s_tk;
+        if (threadIdx.x == 0) s_tk = atomicAdd(A.sp_ticket, 1ull) - A.sp_base;
+        __syncthreads();
+        if (s_tk >= (unsigned long long)A.ntiles * gridDim.y) {
+            // ticket bookkeeping out of step with the launches: touch nothing
+            if (threadIdx.x == 0)
+                __hip_atomic_store(A.sp_err, (int)A.sp_epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        tile = (int64_t)(s_tk / gridDim.y);
+        ry = (int)(s_tk % gridDim.y);
+    } else if (A.nblk > 1) {
         // XCD-aware order: every tile of block b runs on XCD b, whose L2 then
         // holds that block's rows of the split product mode
         const int x = (int)(blockIdx.x % kXcdBlocks);
@@ -316,13 +376,13 @@ void seg_tile_kernel(SegArgs A)
     int col, colc;
     bool cval;
     if constexpr (KB == 1) {
-        col = (int)blockIdx.y * RT + j * VW;
+        col = ry * RT + j * VW;
         cval = col < A.R;
         colc = cval ? col : 0;                        // lanes past R read column 0, never store
     } else {
         // lane gl: block gl % nb2 of the last mode, block (gl / nb2) % nb1 of
         // the one before, then the earlier modes' combined index
-        const int gl = (int)blockIdx.y * LPN + j;
+        const int gl = ry * LPN + j;
         const int nb2 = A.kr[np - 1] / VW, nb1 = A.kr[np - 2] / KB;
         cval = gl < A.R / AW;
         const int g2 = cval ? gl : 0;
@@ -718,9 +778,9 @@ void seg_tile_kernel(SegArgs A)
             store_acc(A.out + row * R, v);
         }
     }
+    float at[AW], bt[AW];                             // the tile's carries (wave 0, group 0)
     if (w == 0 && q == 0 && cval) {
         int ft = s_f[0];
-        float at[AW], bt[AW];
 #pragma unroll
         for (int k = 0; k < AW; ++k) { at[k] = s_a[0][j * AW + k]; bt[k] = s_b[0][j * AW + k]; }
         for (int i = 1; i < 4; ++i) {
@@ -734,11 +794,97 @@ void seg_tile_kernel(SegArgs A)
             }
             ft |= s_f[i];
         }
-        store_acc(A.carry_a + tile * R, at);
-        store_acc(A.carry_b + tile * R, bt);
+        if (A.sp_words) {
+#pragma unroll
+            for (int k = 0; k < AW; ++k) {
+                const int c = col + (k / VW) * kstride + (k % VW);
+                sp_put(A.sp_words + (tile * 2) * R + c, at[k], A.sp_epoch);
+                sp_put(A.sp_words + (tile * 2 + 1) * R + c, bt[k], A.sp_epoch);
+            }
+        } else {
+            store_acc(A.carry_a + tile * R, at);
+            store_acc(A.carry_b + tile * R, bt);
+        }
+    }
+    if (A.sp_words) {
+        // chains this tile closes: the segment its first head closes (started
+        // in tile sp_from[tile]), and at the last tile the segment open at the
+        // end.  Up to 8 lane groups sum strided shares of the chain's middle
+        // tiles for wave 0 group 0's columns, several words in flight each;
+        // group 0 adds the shares in a fixed order to the chain start's closing
+        // partial and the tile's own.
+        constexpr int SPG = 4 * Q < 8 ? 4 * Q : 8;       // lane groups summing a chain
+        constexpr int UW = AW >= 16 ? 1 : 16 / AW;       // tiles in flight per group
+        const int G = w * Q + q;
+        __syncthreads();                                  // s_ab has been read above
+        auto chain = [&](int64_t from, bool tail) {
+            float part[AW];
+            zero(part);
+            if (G < SPG && cval) {
+                for (int64_t t0 = from + 1 + G; t0 < tile; t0 += (int64_t)UW * SPG) {
+                    uint64_t wv[UW][AW];
+#pragma unroll
+                    for (int u = 0; u < UW; ++u) {
+                        const int64_t tt = t0 + (int64_t)u * SPG;
+#pragma unroll
+                        for (int k = 0; k < AW; ++k) {
+                            const int c = col + (k / VW) * kstride + (k % VW);
+                            wv[u][k] = tt < tile ? __hip_atomic_load(A.sp_words + (tt * 2) * R + c, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                                 : ((uint64_t)A.sp_epoch << 32);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < UW; ++u) {
+                        const int64_t tt = t0 + (int64_t)u * SPG;
+#pragma unroll
+                        for (int k = 0; k < AW; ++k) {
+                            float x = __uint_as_float((uint32_t)wv[u][k]);
+                            if ((uint32_t)(wv[u][k] >> 32) != A.sp_epoch) {   // not published yet: wait
+                                const int c = col + (k / VW) * kstride + (k % VW);
+                                x = sp_get(A.sp_words + (tt * 2) * R + c, A.sp_epoch, A.sp_err);
+                            }
+                            part[k] += x;
+                        }
+                    }
+                }
+            }
+            if (G < SPG) {
+#pragma unroll
+                for (int k = 0; k < AW; ++k) s_ab[G][j * AW + k] = part[k];
+            }
+            __syncthreads();
+            if (G == 0 && cval) {
+                float v[AW];
+                if (tail && from == tile) {
+                    // the last tile holds the last segment's head: its own closing partial
+#pragma unroll
+                    for (int k = 0; k < AW; ++k) v[k] = bt[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < AW; ++k) {
+                        const int c = col + (k / VW) * kstride + (k % VW);
+                        v[k] = sp_get(A.sp_words + (from * 2 + 1) * R + c, A.sp_epoch, A.sp_err);
+                    }
+                    for (int g2 = 0; g2 < SPG; ++g2) {
+#pragma unroll
+                        for (int k = 0; k < AW; ++k) v[k] += s_ab[g2][j * AW + k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < AW; ++k) v[k] += at[k];
+                }
+                const int gc = tail ? A.nseg - 1 : H_tile - 1;
+                const int64_t row = ROWMAP ? (int64_t)A.seg_row[gc] : (int64_t)gc;
+                store_acc(A.out + row * R, v);
+            }
+            __syncthreads();
+        };
+        const int64_t from1 = A.sp_from[tile];
+        if (from1 >= 0) chain(from1, false);
+        if (tile == A.ntiles - 1) chain(A.sp_tail_from, true);
     }
     if constexpr (RESID) {
-        if (tid == 0 && blockIdx.y == 0 && A.partial)
+        if (tid == 0 && ry == 0 && A.partial)
             A.partial[tile] = ((s_loss[0] + s_loss[1]) + s_loss[2]) + s_loss[3];
     }
 }

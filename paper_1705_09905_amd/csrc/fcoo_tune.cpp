@@ -1,8 +1,9 @@
 // Per-tensor tuning of one (operation, mode): the paper tunes its launch
-// shape per dataset (Sec. V, Table V); here each candidate tile size (and,
-// for SpMTTKRP, the layout with and without XCD blocks) is built, its
-// operation is timed with HIP events on the caller's stream, and the fastest
-// build is kept.  Host code over the public entry points.
+// shape per dataset (Sec. V, Table V); here each candidate layout -- tile
+// size; for SpMTTKRP plain or XCD blocks split by one of the product modes;
+// for bfloat16 rows the lane chunk, which also sets the waves per SIMD -- is
+// built, its operation is timed with HIP events on the caller's stream, and
+// the fastest is kept.  Host code over the public entry points.
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -43,16 +44,23 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
     fcoo_info_t inf{};
     if (fcoo_info(t, mode, op, &inf) == FCOO_OK) threadlen = inf.threadlen;
 
-    // candidates: each tile size, and for SpMTTKRP with and without XCD
-    // blocks; built on the GPU when the sort key allows it (same arrays)
-    struct Cand { int tile, xcd; };
+    // candidates: each tile size; for SpMTTKRP the plain layout and the XCD
+    // blocks split by each product mode; for bfloat16 rows both lane chunks
+    // (4 columns at 4 waves per SIMD, 8 columns at 3).  Builds run on the GPU
+    // when the sort key allows it (same arrays).
+    struct Cand { int tile, xcd, xmode; };
     std::vector<Cand> cands;
     for (int c = 0; c < ncand; ++c) {
-        cands.push_back({tiles[c], 0});
-        if (op == FCOO_OP_MTTKRP && t->nnz > 0) cands.push_back({tiles[c], kXcds});
+        cands.push_back({tiles[c], 0, 0});
+        if (op == FCOO_OP_MTTKRP && t->nnz > 0)
+            for (int m = 0; m < t->order; ++m)
+                if (m != mode) cands.push_back({tiles[c], kXcds, m + 1});
     }
+    const int nprod = op == FCOO_OP_MTTKRP ? t->order - 1 : 1;
+    std::vector<int> lanes = {0};
+    if (dtype == FCOO_BF16 && R % 4 == 0 && R <= 64 && nprod <= 3) lanes = {4, 8};
     auto build = [&](const Cand &c) -> int {
-        fcoo_opts o{threadlen, c.tile, 0, t->nnz > 0 ? 1 : 0, c.xcd};
+        fcoo_opts o{threadlen, c.tile, 0, t->nnz > 0 ? 1 : 0, c.xcd, c.xmode, 0};
         int r = fcoo_build(t, mode, op, &o, stream);
         if (r == FCOO_EUNSUPPORTED && o.device) {   // sort key over 64 bits: host build
             o.device = 0;
@@ -74,31 +82,45 @@ extern "C" int fcoo_autotune(fcoo_tensor *t, int mode, int op, const void *const
         return fail(FCOO_EHIP, "hipEventCreate");
     }
     float bms = FLT_MAX;
-    size_t bi = 0;
+    size_t bi = 0, cur = 0;                          // best and currently built candidate
+    int blane = 0;
     for (size_t c = 0; c < cands.size() && rc == FCOO_OK; ++c) {
-        if (c > 0 && (rc = build(cands[c]))) break;
-        if ((rc = run_op(t, mode, op, factors, dtype, R, out, stream))) break;   // warm-up
-        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(FCOO_EHIP, "hipEventRecord"); break; }
-        for (int r = 0; r < reps && rc == FCOO_OK; ++r) rc = run_op(t, mode, op, factors, dtype, R, out, stream);
-        if (rc) break;
-        float ms = 0.f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = fail(FCOO_EHIP, "timing");
-            break;
+        if (c > 0) {
+            rc = build(cands[c]);
+            cur = c;
+            if (rc == FCOO_EUNSUPPORTED && cands[c].xcd) {   // e.g. 8 x rows past the int32 range
+                rc = FCOO_OK;
+                continue;
+            }
+            if (rc) break;
         }
-        ms /= (float)reps;
-        if (ms < bms) {
-            bms = ms;
-            bi = c;
+        for (int lc : lanes) {
+            t->b[op][mode].lane_cols = lc;           // a launch choice: no rebuild
+            if ((rc = run_op(t, mode, op, factors, dtype, R, out, stream))) break;   // warm-up
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(FCOO_EHIP, "hipEventRecord"); break; }
+            for (int r = 0; r < reps && rc == FCOO_OK; ++r) rc = run_op(t, mode, op, factors, dtype, R, out, stream);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(FCOO_EHIP, "timing");
+                break;
+            }
+            ms /= (float)reps;
+            if (ms < bms) {
+                bms = ms;
+                bi = c;
+                blane = lc;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(out);
     if (rc) return rc;
-    if (bi != cands.size() - 1 && (rc = build(cands[bi]))) return rc;
-    fcoo_opts o{threadlen, cands[bi].tile, 0, 0, cands[bi].xcd};
+    if (bi != cur && (rc = build(cands[bi]))) return rc;
+    t->b[op][mode].lane_cols = blane;
+    fcoo_opts o{threadlen, cands[bi].tile, 0, 0, cands[bi].xcd, cands[bi].xmode, blane};
     if (best) *best = o;
     if (best_ms) *best_ms = bms;
     return FCOO_OK;

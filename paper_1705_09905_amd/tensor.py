@@ -101,12 +101,14 @@ class Tensor:
     # ---- build / inspect --------------------------------------------------
     def build(self, mode: int, op: str = "mttkrp", threadlen: int = 0, tile_nnz: int = 0,
               host_only: bool = False, device: bool = False, xcd_blocks: int = 0,
-              xcd_mode: int = -1) -> "Tensor":
+              xcd_mode: int = -1, lane_cols: int = 0, single_pass: bool = False) -> "Tensor":
         """F-COO encoding of (op, mode); device=True sorts and encodes on the GPU;
         xcd_blocks=8 (SpMTTKRP) splits the nonzeros into per-XCD blocks by
-        ranges of product mode xcd_mode (-1: the one with the most rows)."""
+        ranges of product mode xcd_mode (-1: the one with the most rows);
+        lane_cols (4 or 8, 0: default) sets the bfloat16 row piece per lane;
+        single_pass finishes segments that cross tiles inside the tile kernel."""
         o = L.fcoo_opts(threadlen, tile_nnz, 1 if host_only else 0, 1 if device else 0, int(xcd_blocks),
-                        int(xcd_mode) + 1)
+                        int(xcd_mode) + 1, int(lane_cols), 1 if single_pass else 0)
         stream = C.c_void_p(0) if host_only else _stream()
         L.check(L.fcoo_build(self._h, int(mode), OPS[op], C.byref(o), stream))
         return self
@@ -114,8 +116,10 @@ class Tensor:
     def autotune(self, mode: int, op: str, factors, tiles: Optional[Sequence[int]] = None,
                  reps: int = 3) -> Dict[str, float]:
         """Time each candidate layout for (op, mode) with these factors (op
-        'ttm': factors[mode] is U; SpMTTKRP also tries XCD blocks) and keep
-        the fastest build.  Returns dict(tile_nnz, threadlen, xcd_blocks, ms)."""
+        'ttm': factors[mode] is U; SpMTTKRP also tries XCD blocks split by each
+        product mode; bfloat16 factors also both lane chunks) and keep the
+        fastest.  Returns dict(tile_nnz, threadlen, xcd_blocks, xcd_mode,
+        lane_cols, ms), xcd_mode -1 when unblocked or by the default mode."""
         if op == "mttkrp":
             fp, R, dt = self._factors(factors, skip=mode)
         else:
@@ -129,7 +133,8 @@ class Tensor:
         L.check(L.fcoo_autotune(self._h, int(mode), OPS[op], fp, dt, R, cand, 0 if tiles is None else len(tiles),
                                 int(reps), C.byref(best), C.byref(ms), _stream()))
         return {"tile_nnz": int(best.tile_nnz), "threadlen": int(best.threadlen),
-                "xcd_blocks": int(best.xcd_blocks), "ms": float(ms.value)}
+                "xcd_blocks": int(best.xcd_blocks), "xcd_mode": int(best.xcd_mode) - 1,
+                "lane_cols": int(best.lane_cols), "ms": float(ms.value)}
 
     def info(self, mode: int, op: str = "mttkrp") -> Dict[str, int]:
         i = L.fcoo_info_t()

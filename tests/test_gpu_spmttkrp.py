@@ -23,12 +23,12 @@ def _fcoo():
 
 
 def _check_mttkrp(t, R, mode, L=16, T=4096, dtype="f32", seed=0, kind="normal", tol=TOL_F32,
-                  exact=False):
+                  exact=False, lane_cols=0):
     Tensor = _fcoo()
     F = synth.small_factors(t.dims, R, seed=seed, kind=kind)
     Fd = [f32(f) if dtype == "f32" else bf16(f) for f in F]
-    tag("mttkrp", t.dims, t.nnz, "R", R, "mode", mode, "L", L, "T", T, dtype)
-    h = Tensor(t.idx, t.vals, t.dims).build(mode, "mttkrp", threadlen=L, tile_nnz=T)
+    tag("mttkrp", t.dims, t.nnz, "R", R, "mode", mode, "L", L, "T", T, dtype, "lane_cols", lane_cols)
+    h = Tensor(t.idx, t.vals, t.dims).build(mode, "mttkrp", threadlen=L, tile_nnz=T, lane_cols=lane_cols)
     dev = [to_dev(f, dtype) for f in Fd]
     M = from_dev(h.spmttkrp(mode, dev))
     exp = cpu.mttkrp(t.dims, t.idx, f32(t.vals), Fd, mode)
@@ -39,12 +39,13 @@ def _check_mttkrp(t, R, mode, L=16, T=4096, dtype="f32", seed=0, kind="normal", 
     return h, dev, M
 
 
-def _check_ttm(t, R, mode, L=16, T=4096, dtype="f32", seed=0, kind="normal", tol=TOL_F32, exact=False):
+def _check_ttm(t, R, mode, L=16, T=4096, dtype="f32", seed=0, kind="normal", tol=TOL_F32, exact=False,
+               lane_cols=0):
     Tensor = _fcoo()
     U = synth.small_factors([t.dims[mode]], R, seed=seed, kind=kind)[0]
     Ud = f32(U) if dtype == "f32" else bf16(U)
-    tag("ttm", t.dims, t.nnz, "R", R, "mode", mode, "L", L, "T", T, dtype)
-    h = Tensor(t.idx, t.vals, t.dims).build(mode, "ttm", threadlen=L, tile_nnz=T)
+    tag("ttm", t.dims, t.nnz, "R", R, "mode", mode, "L", L, "T", T, dtype, "lane_cols", lane_cols)
+    h = Tensor(t.idx, t.vals, t.dims).build(mode, "ttm", threadlen=L, tile_nnz=T, lane_cols=lane_cols)
     Yt, fibd = h.spttm(mode, to_dev(Ud, dtype), return_fibres=True)
     Y = from_dev(Yt)
     fib, exp = cpu.ttm(t.dims, t.idx, f32(t.vals), Ud, mode)
@@ -175,6 +176,23 @@ def test_bf16_lane_chunks_exact():
         _check_mttkrp(t4, 16, mode, dtype="bf16", seed=mode, kind="int", exact=True)
 
 
+@pytest.mark.parametrize("dims,Z", [([300, 200], 20000), ([50, 40, 30], 20000), ([14, 12, 10, 9], 9000),
+                                    ([9, 8, 7, 6, 5], 6000)])
+def test_bf16_lane_cols_every_order_exact(dims, Z):
+    # both lane chunks the autotuner chooses between, for SpMTTKRP with 1..4
+    # product modes (4 columns runs with up to three; with more, and for R not
+    # a multiple of 4 or above 64, the build's choice falls back to 8) and for
+    # SpTTM; integer data, so any summation order gives the oracle's result
+    t = synth.random_small(dims, Z, seed=Z + len(dims), value_kind="int")
+    for lc in (4, 8):
+        for R in (4, 28, 64, 6):
+            for mode in range(len(dims)):
+                _check_mttkrp(t, R, mode, T=1024, dtype="bf16", seed=R + mode, kind="int", exact=True,
+                              lane_cols=lc)
+                _check_ttm(t, R, mode, T=1024, dtype="bf16", seed=R + mode, kind="int", exact=True,
+                           lane_cols=lc)
+
+
 def test_bitwise_repeatable():
     t = synth.zipf_tensor([5000, 4000, 3000], 300000, cfg=21)
     Tensor = _fcoo()
@@ -222,3 +240,29 @@ def test_autotune_keeps_fastest_build_and_stays_correct():
     assert h.info(2, "ttm")["tile_nnz"] == r["tile_nnz"]
     _, Y = cpu.ttm(t.dims, t.idx, f32(t.vals), f32(F[2]), 2)
     assert rel_fro(from_dev(h.spttm(2, Fd[2])), Y) <= TOL_F32
+    # bfloat16 factors: the lane chunk is searched too, and XCD blocks by each product mode
+    Fb = [to_dev(f, "bf16") for f in F]
+    for mode in range(3):
+        tag("autotune bf16 mttkrp mode", mode)
+        r = h.autotune(mode, "mttkrp", Fb, tiles=[2048])
+        inf = h.info(mode)
+        assert r["lane_cols"] in (4, 8) and inf["lane_cols"] == r["lane_cols"]
+        assert inf["xcd_blocks"] == max(1, r["xcd_blocks"])
+        if r["xcd_blocks"] > 1:
+            assert inf["block_mode"] == r["xcd_mode"] and r["xcd_mode"] != mode
+        M = from_dev(h.spmttkrp(mode, Fb))
+        assert rel_fro(M, cpu.mttkrp(t.dims, t.idx, f32(t.vals), [bf16(f) for f in F], mode)) <= TOL_F32
+
+
+def test_device_copy_is_exact():
+    import torch
+    from paper_1705_09905_amd import _lib as L
+    import ctypes as C
+    for n in (16, 4096 + 48, (1 << 24) + 16 * 7):
+        tag("device copy bytes", n)
+        src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        L.check(L.fcoo_device_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n,
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)

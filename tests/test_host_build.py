@@ -140,6 +140,14 @@ def test_error_codes():
     rc = _lib.fcoo_create(2, None, 0, None, None, C.byref(C.c_void_p()))
     assert rc == _lib.FCOO_EINVAL
     assert b"dims" in _lib.fcoo_last_error()
+    assert _code(lambda: h.build(0, "mttkrp", lane_cols=2, host_only=True)) == _lib.FCOO_EINVAL
+    h.build(0, "mttkrp", lane_cols=4, host_only=True)
+    assert h.info(0)["lane_cols"] == 4
+    # the copy kernel's argument checks come before any device work
+    assert _lib.fcoo_device_copy(None, None, 0, None) == _lib.FCOO_OK
+    assert _lib.fcoo_device_copy(C.c_void_p(16), C.c_void_p(32), 24, None) == _lib.FCOO_EINVAL
+    assert _lib.fcoo_device_copy(None, C.c_void_p(32), 16, None) == _lib.FCOO_EINVAL
+    assert _lib.fcoo_device_copy(C.c_void_p(8), C.c_void_p(32), 16, None) == _lib.FCOO_EINVAL
 
 
 def test_mode_and_op_out_of_range_are_einval():
