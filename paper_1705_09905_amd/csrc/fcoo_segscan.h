@@ -566,8 +566,9 @@ void seg_tile_kernel(SegArgs A)
                             const bool d = idx == lastidx;
                             lastidx = idx;
                             dup |= (uint32_t)d << ST;
+                            // a repeated row is taken from last0 when used, so the
+                            // register is left as it is here
                             if (!d) load_raw<FT, VW>(reinterpret_cast<const FT *>(p), rows[ST][0]);
-                            else set_one<FT, VW>(rows[ST][0]);
                         } else {
                             load_raw<FT, VW>(reinterpret_cast<const FT *>(p), rows[ST][qq]);
                         }
@@ -575,6 +576,14 @@ void seg_tile_kernel(SegArgs A)
                 });
                 if constexpr (C0 == 0) {
                     if (more) load_schunk<LPN, SC, K, NPM>(A, j, base + SC, re, snxt);
+                }
+                if constexpr (REUSE) {
+                    // hide from the optimiser that the repeat mask below is the
+                    // branch condition above: otherwise it folds the choice
+                    // between last0 and the new row into the branch's join, which
+                    // then needs each conditional gather to land before the next
+                    // one issues (a wait per step instead of one per batch)
+                    __asm__ volatile("" : "+v"(dup));
                 }
                 float vv[CLF];
                 static_for<CLF>([&](auto sc) {
