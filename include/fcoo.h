@@ -351,7 +351,7 @@ int fcoo_gram(fcoo_tensor *t, int mode, const void *A, int dtype, int R, double 
 
 /*
  * fcoo_device_copy -- copy `bytes` of device memory from src to dst with the
- * library's own plain copy kernel (16-byte loads and stores): the device-copy
+ * library's own plain copy kernel (16-byte streaming loads and stores): the device-copy
  * bandwidth the sparse kernels are measured against, and a kernel of known
  * traffic for calibrating hardware byte counters.  Not part of the method.
  *   src, dst  device, 16-byte aligned, not overlapping (caller-owned).

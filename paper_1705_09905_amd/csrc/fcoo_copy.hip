@@ -8,19 +8,24 @@
 namespace fcoo {
 namespace dev {
 
-// 16-byte elements, four loads in flight per thread, grid-stride.
-__global__ __launch_bounds__(256) void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n)
+// One pass: workgroup b copies the contiguous 16 KB block b (256 threads x 4
+// elements of 16 bytes, streaming loads and stores), so the grid holds one
+// workgroup per block.  On an MI355X this shape moved 1 GiB at 6.3 TB/s
+// (read + write) where a grid-stride loop over a capped grid reached 4.3-5.2
+// and hipMemcpyAsync 4.9.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyPer = 4;                            // elements per thread
+
+__global__ __launch_bounds__(256) void copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        uint4 v[4];
+    const int64_t b = (int64_t)blockIdx.x * (256 * kCopyPer) + threadIdx.x;
+    u32x4 v[kCopyPer];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+    for (int u = 0; u < kCopyPer; ++u)
+        if (b + u * 256 < n) v[u] = __builtin_nontemporal_load(src + b + u * 256);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (int u = 0; u < kCopyPer; ++u)
+        if (b + u * 256 < n) __builtin_nontemporal_store(v[u], dst + b + u * 256);
 }
 
 }  // namespace dev
@@ -37,10 +42,10 @@ extern "C" int fcoo_device_copy(const void *src, void *dst, int64_t bytes, void 
     if (!src || !dst) return fail(FCOO_EINVAL, "src or dst is NULL");
     if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(FCOO_EINVAL, "src and dst must be 16-byte aligned");
     const int64_t n = bytes / 16;
-    int64_t g = (n + 256 * 4 - 1) / (256 * 4);
-    if (g > 256 * 16) g = 256 * 16;                   // 16 workgroups per CU, then grid-stride
+    const int64_t g = (n + 256 * dev::kCopyPer - 1) / (256 * dev::kCopyPer);
+    if (g > 0x7fffffff) return fail(FCOO_EINVAL, "bytes = %lld: too large for one launch", (long long)bytes);
     hipLaunchKernelGGL(dev::copy_kernel, dim3((unsigned)g), dim3(256), 0, (hipStream_t)stream,
-                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+                       static_cast<const dev::u32x4 *>(src), static_cast<dev::u32x4 *>(dst), n);
     FCOO_HIP(hipGetLastError());
     return FCOO_OK;
 }
