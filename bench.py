@@ -16,7 +16,9 @@ The same JSON line carries CP-ALS (Algorithm 1) on the planted rank-16
 tensor 200,000 x 150,000 x 100,000 with 100M uniform nonzeros at R = 16,
 ten sweeps with float32 and with bfloat16 factor storage: seconds per sweep,
 the fit of every sweep, and (with the CPU leg) the float64 oracle's fits and
-the CP model at sampled nonzeros against the oracle's.
+the CP model at sampled nonzeros against the oracle's; and CP-ALS on the
+order-4 Zipf tensor 50,000 x 20,000 x 5,000 x 1,000 with 50M nonzeros at
+R = 32 (seconds per sweep and fits, float32 and bfloat16).
 
 The roofline object describes the dominant kernel (the SpMTTKRP or SpTTM
 tile kernel with the largest total time), timed alone with HIP events that
@@ -324,6 +326,46 @@ def cp_planted(args, log, cpu_rec):
     return rec
 
 
+def cp_order4(args, log):
+    """CP-ALS (Algorithm 1) on the order-4 Zipf(1.1) tensor 50,000 x 20,000 x
+    5,000 x 1,000 with 50M nonzeros, R = 32: float32 and bfloat16 factor
+    storage from the same start, layouts autotuned per storage type,
+    seconds per sweep (median of sweeps 2..S) and the fit of every sweep.
+    Its parity against the oracle (fits and the CP model at sampled
+    nonzeros) is the order-4 GPU test; no oracle runs here."""
+    import torch
+    import synth
+    from paper_1705_09905_amd import Tensor
+    cfg, R, S = 2, 32, args.cp4_sweeps
+    t0 = time.time()
+    t = synth.config_tensor(cfg)
+    log(f"generated {t.name} Z={t.nnz} in {time.time() - t0:.1f}s")
+    h = Tensor(t.idx, t.vals, t.dims)
+    init = synth.factors(t.dims, R, cfg, role="init")
+    rec = {"workload": f"{t.name}: CP-ALS, R = {R}, {S} sweeps", "dims": t.dims, "nnz": t.nnz, "R": R,
+           "sweeps": S, "layout": {}}
+    for dt in ("f32", "bf16"):
+        Ft = [torch.tensor(a.astype(np.float32), device="cuda").to(
+            torch.float32 if dt == "f32" else torch.bfloat16).contiguous() for a in init]
+        layout = {}
+        for m in range(t.order):
+            r = h.autotune(m, "mttkrp", Ft, tiles=[2048, 4096, 8192])
+            layout[f"mode{m}"] = {k: r[k] for k in ("tile_nnz", "xcd_blocks", "xcd_mode", "lane_cols")}
+        del Ft
+        rec["layout"][dt] = layout
+        fits, secs, _ = cp_gpu(h, t, R, S, init, dt)
+        rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
+                   "s_per_iter_min": round(float(np.min(secs)), 6),
+                   "s_per_iter_max": round(float(np.max(secs)), 6),
+                   "fits": [float(f"{f:.6g}") for f in fits]}
+        log(f"order-4 cp-als {dt}: {rec[dt]['s_per_iter'] * 1e3:.3f} ms/sweep, layout {layout}")
+    rec["bf16_speedup_vs_f32"] = round(rec["f32"]["s_per_iter"] / rec["bf16"]["s_per_iter"], 3)
+    rec["max_abs_fit_diff_bf16_vs_f32"] = float(
+        f"{max(abs(a - b) for a, b in zip(rec['f32']['fits'], rec['bf16']['fits'])):.3g}")
+    del h
+    return rec
+
+
 def kernel_symbol(op, R, N):
     """Demangled name of the tile-kernel instantiation that runs (op, R)
     with float32 factors (16-byte lanes: 4 columns per lane)."""
@@ -487,6 +529,8 @@ def main():
     ap.add_argument("--detail", action="store_true", help="print per-operation lines to stderr")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (scales traffic counters)")
+    ap.add_argument("--cp4-sweeps", type=int, default=10,
+                    help="CP-ALS sweeps on the order-4 Zipf 50M tensor (0: skip that part)")
     ap.add_argument("--cp-sweeps", type=int, default=10,
                     help="CP-ALS sweeps on the planted 100M tensor (0: skip that part)")
     ap.add_argument("--cp-model-sample", type=int, default=1_000_000,
@@ -755,6 +799,9 @@ def main():
     torch.cuda.synchronize()
     if args.cp_sweeps > 0:
         out["cp_als"] = cp_planted(args, log, out["cpu_baseline"])
+    torch.cuda.synchronize()
+    if args.cp4_sweeps > 0:
+        out["cp_als_order4"] = cp_order4(args, log)
     print(json.dumps(out), flush=True)
 
 
