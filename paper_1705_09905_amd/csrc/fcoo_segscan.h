@@ -296,21 +296,26 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 
 // Waves per SIMD.  The gathers' latency is what the waves wait on, so the
 // wave count is held up by launch bounds, with the gather batch (registers
-// of rows in flight per lane) sized to fit: every float32 form runs 4 waves
-// (128 VGPRs; the fused residual spills a few registers there and is still
-// faster) with a half batch, and so does bfloat16 in 4-column lane chunks
-// (8-byte row pieces, so a quarter batch holds as many rows); bfloat16 in
-// 8-column chunks runs 3 (133-168 VGPRs) with a half batch; the one-lane
-// residual form is left unconstrained.
+// of rows in flight per lane) sized to fit: float32 SpMTTKRP runs 3 waves
+// with a full batch (more rows in flight per wave than 4 waves with a half
+// batch, once a batch's gathers issue back to back); the other float32
+// forms run 4 waves (128 VGPRs; the fused residual spills a few registers
+// there and is still faster) with a half batch, and so does bfloat16 in
+// 4-column lane chunks (8-byte row pieces, so a quarter batch holds as many
+// rows); bfloat16 in 8-column chunks runs 3 (133-168 VGPRs) with a half
+// batch; the one-lane residual form is left unconstrained.
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool KRON>
 struct TileShape {
     static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && (!RESID || LPN > 1);
+    // float32 SpMTTKRP (two or more product modes): 3 waves with a double batch
+    static constexpr bool F32MULTI = F32PLAIN && !RESID && !KRON && NP >= 2;
     static constexpr bool B16HALF = sizeof(FT) == 2 && VW == 4 && NP >= 1 && !RESID && !KRON;
     static constexpr bool B16ONE = sizeof(FT) == 2 && NP == 1 && !RESID && !KRON;
-    static constexpr int waves = (F32PLAIN || B16HALF) ? 4 : B16ONE ? 3
+    static constexpr int waves = F32MULTI ? 3 : (F32PLAIN || B16HALF) ? 4 : B16ONE ? 3
                                : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
     // registers of raw rows per lane for one gather batch
-    static constexpr int batch_regs = B16HALF ? 16 : (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
+    static constexpr int batch_regs = F32MULTI ? 64 : B16HALF ? 16
+                                    : (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
 };
 
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool ROWMAP, bool KRON = false, int KB = 1>

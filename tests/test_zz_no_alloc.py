@@ -82,6 +82,25 @@ def test_noalloc_xcd_blocked_build():
         assert rel_fro(from_dev(got), cpu.mttkrp(t.dims, t.idx, f32(t.vals), Fh, mode)) <= TOL_F32
 
 
+def test_noalloc_on_a_single_pass_build_keeps_the_fixup_pass():
+    # a single-pass build's words are allocated on first use, so the no-alloc
+    # entry point runs such a build with the fix-up pass and its fixed scratch
+    import torch
+    from paper_1705_09905_amd import Tensor, _lib as L
+    t = synth.random_small([200, 150, 100], 80_003, seed=7)
+    F = synth.small_factors(t.dims, 16, seed=7)
+    Fd = [to_dev(f32(f)) for f in F]
+    h = Tensor(t.idx, t.vals, t.dims).build(0, "mttkrp", tile_nnz=256, single_pass=True)
+    tag("noalloc on a single-pass build", t.dims, t.nnz)
+    got = torch.full((t.dims[0], 16), float("nan"), dtype=torch.float32, device="cuda")
+    L.check(_noalloc(h, 0, Fd, got))
+    ref = h.spmttkrp(0, Fd)
+    torch.cuda.synchronize()
+    exp = cpu.mttkrp(t.dims, t.idx, f32(t.vals), [f32(f) for f in F], 0)
+    assert rel_fro(from_dev(got), exp) <= TOL_F32 and rel_fro(from_dev(ref), exp) <= TOL_F32
+    assert h.info(0)["sp_gave_up"] == 0
+
+
 def test_noalloc_refuses_scratch_beyond_its_array():
     import torch
     from paper_1705_09905_amd import _lib as L
