@@ -395,11 +395,13 @@ void seg_tile_kernel(SegArgs A)
         colc = col;
     }
     const int R = A.R;
-    const uint64_t R4 = (uint64_t)R * sizeof(FT);
+    // row bytes fit 32 bits (R <= 256), so a gather address is one 32 x 32 -> 64
+    // multiply-add onto the factor's base
+    const uint32_t R4 = (uint32_t)R * (uint32_t)sizeof(FT);
     // RESID: factor row of the index mode for an output row (blocks add block * rows)
     auto own_row = [&](int r) -> int64_t { return A.nblk > 1 ? (int64_t)(r % A.rows_own) : (int64_t)r; };
     const char *fb[NPM];
-    uint64_t R4k[NPM];                                // KRON: row bytes of each product mode
+    uint32_t R4k[NPM];                                // KRON: row bytes of each product mode
     if constexpr (KRON) {
         // digits of this lane's first column, last product mode fastest (with
         // column blocks, the second-to-last digit starts this lane's KB-piece)
@@ -410,7 +412,7 @@ void seg_tile_kernel(SegArgs A)
                 const int d = rem % A.kr[qq];
                 rem /= A.kr[qq];
                 fb[qq] = reinterpret_cast<const char *>(A.fac[qq]) + (size_t)d * sizeof(FT);
-                R4k[qq] = (uint64_t)A.kr[qq] * sizeof(FT);
+                R4k[qq] = (uint32_t)A.kr[qq] * (uint32_t)sizeof(FT);
             } else {
                 fb[qq] = nullptr;
                 R4k[qq] = 0;
@@ -566,7 +568,7 @@ void seg_tile_kernel(SegArgs A)
 #pragma unroll
                     for (int qq = 0; qq < NPM; ++qq) {
                         const int idx = sc_idx<LPN, C0 + ST, K, NPM>(scur, qq);
-                        const char *p = fb[qq] + (uint64_t)(uint32_t)idx * R4;
+                        const char *p = fb[qq] + (uint64_t)(uint32_t)idx * (uint64_t)R4;
                         if (REUSE && qq == 0) {
                             const bool d = idx == lastidx;
                             lastidx = idx;
@@ -624,6 +626,17 @@ void seg_tile_kernel(SegArgs A)
 #pragma unroll
                         for (int k = 0; k < VW; ++k) acc[k] += vv[ST] * h[k];
                     });
+                } else if (NP == 1 && !RESID && __ballot(n < CLF) == 0ull) {
+                    // every lane group holds the whole batch (only a run's end
+                    // is short), so no step needs the bound check; kept to one
+                    // product mode without the residual, where the copy of the
+                    // loop body costs no spills
+                    static_for<CLF>([&](auto sc) {
+                        constexpr int ST = decltype(sc)::value;
+                        float h[VW];
+                        hrow(sc, h);
+                        step(h, vv[ST], hm, ST, CLF);
+                    });
                 } else {
                     static_for<CLF>([&](auto sc) {
                         constexpr int ST = decltype(sc)::value;
@@ -653,7 +666,7 @@ void seg_tile_kernel(SegArgs A)
 #pragma unroll
                     for (int qq = 0; qq < NPM; ++qq) {
                         const int idx = bcast_imm<LPN, ST % LPN>(cur.idx[ST / LPN][qq]);
-                        const FT *p = reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * R4k[qq]);
+                        const FT *p = reinterpret_cast<const FT *>(fb[qq] + (uint64_t)(uint32_t)idx * (uint64_t)R4k[qq]);
                         if constexpr (KRON && KB > 1) {
                             if (qq < np - 2) load_raw<FT, 1>(p, ks[ST - S0][qq]);
                             else if (qq == np - 2) load_raw<FT, KB>(p, kp[ST - S0]);
