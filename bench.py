@@ -162,6 +162,7 @@ def cpu_baseline(t, Rs, sample_nnz, threads, reps=5):
     vals = t.vals[:Zs].astype(np.float32).astype(np.float64)
     N = t.order
     total_bytes, total_s, used = 0, 0.0, 1
+    per_op = {}
     groups = [cpu.ttm_group(t.dims, idx, m) for m in range(N)]
 
     def med(fn):
@@ -178,18 +179,43 @@ def cpu_baseline(t, Rs, sample_nnz, threads, reps=5):
         for m in range(N):
             dt, (_, used) = med(lambda: cpu.mttkrp(t.dims, idx, vals, F, m, nthreads=threads,
                                                    return_threads=True))
+            per_op[("mttkrp", m, R)] = dt
             total_s += dt
             nseg = len(np.unique(idx[m]))
             total_bytes += op_bytes("mttkrp", Zs, N, R, nseg, t.dims[m], -(-Zs // 16))
             dt, (fib, _, _) = med(lambda: cpu.ttm(t.dims, idx, vals, F[m], m, group=groups[m],
                                                   nthreads=threads, return_threads=True))
+            per_op[("ttm", m, R)] = dt
             total_s += dt
             total_bytes += op_bytes("ttm", Zs, N, R, fib.shape[0], t.dims[m], -(-Zs // 16))
     return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": int(used),
             "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"first {Zs} of {t.nnz} nonzeros (seeded shuffle order), SpMTTKRP + SpTTM, "
                       f"every mode, R in {list(Rs)}, float64; per operation 1 warm-up then the "
-                      f"median of {reps} runs, {total_s:.2f} s summed (fibre grouping excluded)"}
+                      f"median of {reps} runs, {total_s:.2f} s summed (fibre grouping excluded)",
+            "_per_op_s": per_op, "_sample_nnz": Zs}
+
+
+def op_parity(t, Rs, outs, threads):
+    """Full-size parity of the step's outputs (the last timed launch of each
+    operation, which is bitwise repeatable): relative Frobenius error against
+    the float64 C oracle on the whole tensor, from the same float32 inputs."""
+    from oracle import cpu
+    import synth
+    vals = t.vals.astype(np.float32).astype(np.float64)
+    N = t.order
+    err = {}
+    for R in Rs:
+        F = [f.astype(np.float32).astype(np.float64) for f in synth.factors(t.dims, R, WORKLOAD_CFG)]
+        for m in range(N):
+            want = cpu.mttkrp(t.dims, t.idx, vals, F, m, nthreads=threads)
+            got = outs[("mttkrp", m, R)].cpu().numpy().astype(np.float64)
+            err[("mttkrp", m, R)] = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+            _, want = cpu.ttm(t.dims, t.idx, vals, F[m], m, nthreads=threads)
+            got = outs[("ttm", m, R)].cpu().numpy().astype(np.float64)
+            err[("ttm", m, R)] = (float(np.linalg.norm(got - want) / np.linalg.norm(want))
+                                  if got.shape == want.shape else float("inf"))
+    return err
 
 
 def cp_oracle(t, R, sweeps, init, record=None, storage="f64"):
@@ -207,7 +233,10 @@ def cp_oracle(t, R, sweeps, init, record=None, storage="f64"):
 def cp_gpu(h, t, R, sweeps, init, dtype, keep_after=()):
     """CP-ALS sweeps on the device; wall time of every sweep (each call ends
     with the 8-byte fit read-back).  Factors and lambda after the sweeps in
-    `keep_after` are copied to the host outside the timed calls."""
+    `keep_after` are copied to the host outside the timed calls.  Returns
+    fits, seconds and kept factors per sweep; each sweep's pseudo-inverse
+    mask (bit n: mode n's normal equations took the pseudo-inverse) is left
+    in cp_gpu.used_pinv."""
     import torch
     from paper_1705_09905_amd import _lib
     tdt = torch.float32 if dtype == "f32" else torch.bfloat16
@@ -219,6 +248,7 @@ def cp_gpu(h, t, R, sweeps, init, dtype, keep_after=()):
     stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     code = _lib.FCOO_F32 if dtype == "f32" else _lib.FCOO_BF16
     fits, secs, kept = [], [], {}
+    cp_gpu.used_pinv = []
     torch.cuda.synchronize()
     for s in range(sweeps):
         t0 = time.perf_counter()
@@ -226,6 +256,7 @@ def cp_gpu(h, t, R, sweeps, init, dtype, keep_after=()):
                                          1 if s else 0, C.byref(fit), C.byref(used), stream))
         secs.append(time.perf_counter() - t0)
         fits.append(float(fit.value))
+        cp_gpu.used_pinv.append(int(used.value))
         if s + 1 in keep_after:
             kept[s + 1] = ([f.to(torch.float64).cpu().numpy() for f in F], lam.cpu().numpy())
     return fits, secs, kept
@@ -286,7 +317,8 @@ def cp_planted(args, log, cpu_rec):
         rec[dt] = {"s_per_iter": round(float(np.median(secs[1:] if len(secs) > 1 else secs)), 6),
                    "s_per_iter_min": round(float(np.min(secs)), 6),
                    "s_per_iter_max": round(float(np.max(secs)), 6),
-                   "fits": [float(f"{f:.6g}") for f in fits]}
+                   "fits": [float(f"{f:.6g}") for f in fits],
+                   "used_pinv": list(cp_gpu.used_pinv)}
         log(f"cp-als {dt}: {rec[dt]['s_per_iter'] * 1e3:.3f} ms/sweep")
     rec["bf16_speedup_vs_f32"] = round(rec["f32"]["s_per_iter"] / rec["bf16"]["s_per_iter"], 3)
     del h
@@ -378,6 +410,19 @@ def kernel_symbol(op, R, N):
     npt = np_ if np_ <= 3 else 0
     return (f"void fcoo::dev::seg_tile_kernel<float, 4, {lpn}, {npt}, false, "
             f"{'true' if op == 'mttkrp' else 'false'}, false, 1>(fcoo::dev::SegArgs)")
+
+
+def rank_tile(R):
+    """Columns one tile-kernel workgroup covers for float32 factors: 4 per
+    lane, lanes per nonzero the next power of two of R / 4 (at most 16); 64
+    one-column lanes when R is not a multiple of 4."""
+    if R % 4:
+        return 64
+    lanes = R // 4
+    lpn = 1
+    while lpn < lanes:
+        lpn *= 2
+    return min(lpn, 16) * 4
 
 
 def load_traffic(khash):
@@ -536,6 +581,8 @@ def main():
     ap.add_argument("--cp-model-sample", type=int, default=1_000_000,
                     help="nonzeros at which the CPU leg compares the CP model with the oracle's")
     ap.add_argument("--ttmc-rank", type=int, default=16, help="SpTTMc rank per mode (0: skip)")
+    ap.add_argument("--records", default="",
+                    help="also write the per-operation records, one JSON line each, to this file")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -570,10 +617,13 @@ def main():
     facs = {R: [torch.tensor(f.astype(np.float32), device=dev)
                 for f in synth.factors(t.dims, R, WORKLOAD_CFG)] for R in Rs}
     t0 = time.time()
+    build_ms = {}
     for m in range(t.order):
         for op in ("mttkrp", "ttm"):
             tile = (args.tile_ttm or args.tile) if op == "ttm" else args.tile
+            tb = time.time()
             h.build(m, op, threadlen=args.threadlen, tile_nnz=tile or 4096)
+            build_ms[(op, m)] = (time.time() - tb) * 1e3
     build_s = time.time() - t0
     log(f"F-COO built and uploaded (6 builds) in {build_s:.1f}s")
     tiles = {}
@@ -787,14 +837,62 @@ def main():
                          "GBps_per_mode": [round(kb[m] / km[m] / 1e6, 1) for m in range(N)],
                          "GFLOPs_per_mode": [round(t.nnz * W * N / km[m] / 1e6, 1) for m in range(N)]}
         log(f"spttmc R={Rk}: {out['spttmc']['tile_ms_per_mode']} ms")
+    oracle_s, parity, sample_nnz, threads = {}, {}, None, None
     if not args.no_cpu:
         threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         os.environ.setdefault("OMP_PROC_BIND", "close")
         t0 = time.time()
         out["cpu_baseline"] = cpu_baseline(t, Rs, args.cpu_sample, threads)
+        oracle_s = out["cpu_baseline"].pop("_per_op_s")
+        sample_nnz = out["cpu_baseline"].pop("_sample_nnz")
         log(f"cpu baseline in {time.time() - t0:.1f}s")
+        t0 = time.time()
+        parity = op_parity(t, Rs, outs, threads)
+        log(f"full-size parity of the step's outputs in {time.time() - t0:.1f}s: "
+            f"max rel err {max(parity.values()):.2e}")
     else:
         out["cpu_baseline"] = None
+    # one record per measured operation (op, mode, R)
+    records = []
+    for (op, m, R) in launches:
+        inf = infos[(op, m)]
+        ts = per[(op, m, R)]
+        B = op_bytes(op, t.nnz, N, R, nsegs[(op, m)], t.dims[m], inf["npart"])
+        F = op_flops(op, t.nnz, N, R)
+        med = float(np.median(ts))
+        trec = None
+        if tr is not None:
+            lay = tr.get("layout", {}).get(op)
+            if lay is not None and inf["tile_nnz"] == lay["tile_nnz"] and \
+                    (inf["xcd_blocks"] > 1) == (lay["xcd_blocks"] > 1):
+                trec = tr.get("kernels", {}).get(kernel_symbol(op, R, N))
+        records.append({
+            "config": t.name, "op": op, "mode": m, "R": R, "dtype": "f32", "Z": t.nnz,
+            ("nseg" if op == "mttkrp" else "nfib"): int(nsegs[(op, m)]),
+            "threadlen": args.threadlen, "tile_nnz": inf["tile_nnz"], "xcd_blocks": inf["xcd_blocks"],
+            "lane_cols": inf["lane_cols"], "rank_tile": rank_tile(R),
+            "t_gpu_ms": {"median": round(med, 4), "min": round(float(np.min(ts)), 4),
+                         "max": round(float(np.max(ts)), 4), "n": len(ts)},
+            "B_alg": int(B), "GBps_eff": round(B / med / 1e6, 1),
+            "pct_hbm_spec_alg": round(100 * B / med / 1e6 / HBM_PEAK_GBPS, 1),
+            "pct_hbm_copy_alg": round(100 * B / med / 1e6 / cbw, 1),
+            "GFLOPs": round(F / med / 1e6, 1),
+            "B_compulsory": int(compulsory_bytes(op, t.nnz, N, R, nsegs[(op, m)], t.dims[m], inf["npart"],
+                                                 distinct, m)),
+            "rocprof_fetch_bytes": None if trec is None else trec["fetch_bytes_per_launch"],
+            "rocprof_write_bytes": None if trec is None else trec["write_bytes_per_launch"],
+            "rocprof_note": None if trec is None else "per launch, mean over the modes of this kernel class",
+            "t_build_ms": round(build_ms[(op, m)], 1),
+            "t_oracle_ms": None if (op, m, R) not in oracle_s else round(1e3 * oracle_s[(op, m, R)], 1),
+            "oracle_sample_nnz": sample_nnz, "oracle_threads": threads,
+            "cpu_model": None if args.no_cpu else cpu_model(),
+            "rel_fro_err_vs_oracle": None if (op, m, R) not in parity else float(f"{parity[(op, m, R)]:.3g}"),
+        })
+    out["records"] = records
+    if args.records:
+        with open(args.records, "w") as f:
+            for r in records:
+                f.write(json.dumps(r) + "\n")
     del h, facs, outs
     torch.cuda.synchronize()
     if args.cp_sweeps > 0:

@@ -28,3 +28,38 @@ def test_byte_models_on_a_tiny_case():
     assert bench.op_bytes("ttm", Z, N, R, nseg, In, P) - \
         bench.compulsory_bytes("ttm", Z, N, R, nseg, In, P, [3, 10, 10], 0) == (Z - 3) * R * 4
     assert len(bench.kernel_hash()) == 16
+
+
+def test_rank_tile_follows_the_launch_rule():
+    sys.path.insert(0, ROOT)
+    import bench
+    # 4 columns per lane, lanes per nonzero the next power of two of R / 4 (<= 16);
+    # one-column lanes (64 of them) when R is not a multiple of 4
+    assert [bench.rank_tile(R) for R in (4, 8, 16, 32, 64, 128, 256)] == [4, 8, 16, 32, 64, 64, 64]
+    assert bench.rank_tile(12) == 16 and bench.rank_tile(40) == 64
+    assert bench.rank_tile(3) == 64 and bench.rank_tile(100) == 64
+
+
+def test_op_parity_is_zero_for_the_oracles_own_outputs():
+    # the record's full-size check compares outputs with the float64 oracle;
+    # fed the oracle's own results (as float32 tensors), the error is rounding only
+    import numpy as np
+    import torch
+    sys.path.insert(0, ROOT)
+    import bench
+    import synth
+    from oracle import cpu
+    t = synth.random_small([30, 20, 10], 3000, seed=7)
+    old = bench.WORKLOAD_CFG
+    outs = {}
+    vals = t.vals.astype(np.float32).astype(np.float64)
+    for R in (4, 8):
+        F = [f.astype(np.float32).astype(np.float64) for f in synth.factors(t.dims, R, old)]
+        for m in range(3):
+            outs[("mttkrp", m, R)] = torch.tensor(cpu.mttkrp(t.dims, t.idx, vals, F, m).astype(np.float32))
+            outs[("ttm", m, R)] = torch.tensor(cpu.ttm(t.dims, t.idx, vals, F[m], m)[1].astype(np.float32))
+    err = bench.op_parity(t, (4, 8), outs, 2)
+    assert len(err) == 12 and max(err.values()) < 1e-7
+    # a wrong row is seen
+    outs[("ttm", 1, 8)][3, 2] += 1.0
+    assert bench.op_parity(t, (4, 8), outs, 2)[("ttm", 1, 8)] > 1e-4
