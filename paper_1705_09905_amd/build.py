@@ -28,6 +28,7 @@ SOURCES = [
     "fcoo_host.cpp",
     "fcoo_tune.cpp",
     "fcoo_devbuild.hip",
+    "fcoo_sort.hip",
     "fcoo_ops.hip",
     "fcoo_cp.hip",
     "fcoo_noalloc.hip",

@@ -2,7 +2,7 @@
 // Same arrays as the host builder, bit for bit:
 //   1. packed 64-bit key per nonzero (index modes, then product modes, each
 //      in ascending mode order, lower modes in the higher bits) and a stable
-//      radix sort of (key, input position) -- rocPRIM's device radix sort;
+//      radix sort of (key, input position) (fcoo_sort.hip);
 //   2. product-mode indices decoded from the sorted keys (their low bits),
 //      values gathered through the sorted positions, and the segment heads
 //      (index-mode part of the key changes);
@@ -16,8 +16,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include <vector>
 
@@ -257,19 +255,20 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
     hipLaunchKernelGGL(dev::key_kernel, dim3(grid_of(Z)), dim3(256), 0, s, ka, k0, p0);
     FCOO_HIP(hipGetLastError());
     const int end_bit = total > 0 ? total : 1;
-    size_t sort_bytes = 0, scan_bytes = 0;
-    FCOO_HIP(rocprim::radix_sort_pairs(nullptr, sort_bytes, k0, k1, p0, p1, (size_t)Z, 0, end_bit, s));
-    FCOO_HIP(rocprim::inclusive_scan(nullptr, scan_bytes, head, cum, (size_t)Z, rocprim::plus<int32_t>(), s));
-    char *work;
-    if ((rc = tmp.get(&work, (int64_t)(sort_bytes > scan_bytes ? sort_bytes : scan_bytes)))) return rc;
-    FCOO_HIP(rocprim::radix_sort_pairs(work, sort_bytes, k0, k1, p0, p1, (size_t)Z, 0, end_bit, s));
+    const int64_t wsort = sort_work_ints(Z), wscan = scan_work_ints(Z);
+    int32_t *work;
+    if ((rc = tmp.get(&work, wsort > wscan ? wsort : wscan))) return rc;
+    int passes = 0;
+    if ((rc = sort_pairs_u64(k0, k1, p0, p1, Z, end_bit, work, s, &passes))) return rc;
+    uint64_t *ks = (passes & 1) ? k1 : k0;            // the sorted pairs
+    uint32_t *ps = (passes & 1) ? p1 : p0;
 
     // 2. sorted per-nonzero arrays (4 zero entries of padding, as uploaded by the host builder)
     int64_t acct = 0;
     dev::GatherArgs ga{};
     ga.vals = t->d_coo_val;
-    ga.key = k1;
-    ga.pos = p1;
+    ga.key = ks;
+    ga.pos = ps;
     ga.np = (int)b.pmodes.size();
     for (int q = ga.np - 1, sh = 0; q >= 0; --q) {   // last product mode in the lowest bits
         if ((rc = alloc_dev(&b.d_pidx[q], Z, 4, s, &acct))) return rc;
@@ -289,7 +288,7 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
     FCOO_HIP(hipGetLastError());
 
     // 3. segment ordinals
-    FCOO_HIP(rocprim::inclusive_scan(work, scan_bytes, head, cum, (size_t)Z, rocprim::plus<int32_t>(), s));
+    if ((rc = scan_i32(head, cum, Z, true, work, s))) return rc;
 
     // 4. flags, tiles, segments
     const int64_t bfw = (Z + 31) / 32, sfw = (P + 31) / 32;
@@ -319,7 +318,7 @@ int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int L, int T, in
         return rc;
     }
     dev::SegArgsB sa{};
-    sa.key = k1;
+    sa.key = ks;
     sa.head = head;
     sa.cum = cum;
     int sh = pbits;

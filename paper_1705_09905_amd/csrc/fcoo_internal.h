@@ -145,6 +145,17 @@ int upload_i32(int32_t **dst, const std::vector<int32_t> &v, int64_t pad, hipStr
 // (heads_before[t] = heads before nonzero t * tile_nnz, t = 0 .. ntiles) and b.seg
 void finish_tiles(const fcoo_tensor *t, Built &b, int mode, int op, const std::vector<int64_t> &heads_before);
 // the F-COO build of one (op, mode) on the GPU (same arrays as the host build)
+// Device primitives of the GPU build (fcoo_sort.hip).  sort_pairs_u64: stable
+// radix sort of n (key, value) pairs by the key's bits below end_bit,
+// ping-ponging between the two buffers; the result is in (k0, v0) if
+// *passes is even, else in (k1, v1).  scan_i32: prefix sum of n int32 (out
+// may not alias in).  `work` holds sort_work_ints(n) / scan_work_ints(n)
+// int32 of device scratch.  Both enqueue on s and return an FCOO_* code.
+int64_t sort_work_ints(int64_t n);
+int64_t scan_work_ints(int64_t n);
+int sort_pairs_u64(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int64_t n, int end_bit,
+                   int32_t *work, hipStream_t s, int *passes);
+int scan_i32(const int32_t *in, int32_t *out, int64_t n, bool inclusive, int32_t *work, hipStream_t s);
 int build_on_device(fcoo_tensor *t, Built &b, int mode, int op, int threadlen, int tile_nnz, int nblk,
                     int xmode, hipStream_t s);
 // XCD blocks of a SpMTTKRP build (nblk 0 / 1: none), split by ranges of product
