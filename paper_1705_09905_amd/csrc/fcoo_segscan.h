@@ -452,8 +452,13 @@ void seg_tile_kernel(SegArgs A)
     constexpr int SC = FAST ? 4 * LPN * K : CL;                        // steps per super-chunk
     static_assert(!FAST || (SC % CLF == 0 && SC <= 64), "super-chunk shape");
     // SpMTTKRP: consecutive nonzeros often share the first product-mode
-    // index (its order within a segment is sorted); such rows are not re-read
-    constexpr bool REUSE = FAST && ROWMAP && NP >= 2;
+    // index (its order within a segment is sorted); such rows are not re-read.
+    // That saves cache requests at the price of a held row and a select per
+    // step: it pays where one gather instruction covers 16 rows or more (4
+    // lanes per row or fewer) or there are three product modes, and cost
+    // float32 with two product modes at 8 or more lanes per row 4% on the
+    // Zipf 20M tensor, so that form re-reads the row
+    constexpr bool REUSE = FAST && ROWMAP && NP >= 2 && !(sizeof(FT) == 4 && NP == 2 && LPN >= 8);
     Chunk<U, NPM> cur;
     SChunk<K, NPM> scur;
     if (rs < re) {
