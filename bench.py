@@ -548,7 +548,7 @@ def run_extra(args, log):
             torch.cuda.synchronize()
             ms = a.elapsed_time(b) / steps
             B = mttkrp_bytes(4 if dt == "f32" else 2, own=True)
-            rec[dt] = {"ms_per_step": round(ms, 4), "losses": [round(float(x), 6) for x in losses],
+            rec[dt] = {"ms_per_step": round(ms, 4), "losses": [round(float(x.detach()), 6) for x in losses],
                        "fused_resid_bytes_per_step": B, "GBps_fused_resid_bytes": round(B / ms / 1e6, 1)}
             log(f"gradient CP {dt}: {ms:.3f} ms/step")
         rec["value"], rec["unit"], rec["dtype"] = rec["f32"]["ms_per_step"] / 1e3, "s/step", "f32"

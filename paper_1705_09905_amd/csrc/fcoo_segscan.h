@@ -455,10 +455,12 @@ void seg_tile_kernel(SegArgs A)
     // index (its order within a segment is sorted); such rows are not re-read.
     // That saves cache requests at the price of a held row and a select per
     // step: it pays where one gather instruction covers 16 rows or more (4
-    // lanes per row or fewer) or there are three product modes, and cost
+    // lanes per row or fewer) or there are three product modes, but cost
     // float32 with two product modes at 8 or more lanes per row 4% on the
-    // Zipf 20M tensor, so that form re-reads the row
-    constexpr bool REUSE = FAST && ROWMAP && NP >= 2 && !(sizeof(FT) == 4 && NP == 2 && LPN >= 8);
+    // Zipf 20M tensor, and the fused residual form (which also holds the
+    // segment's own row) 18% in bfloat16 on the 200M tensor, so those forms
+    // re-read the row
+    constexpr bool REUSE = FAST && ROWMAP && NP >= 2 && !RESID && !(sizeof(FT) == 4 && NP == 2 && LPN >= 8);
     Chunk<U, NPM> cur;
     SChunk<K, NPM> scur;
     if (rs < re) {
