@@ -303,7 +303,9 @@ __device__ __forceinline__ void select_raw(bool take_a, const Raw<FT, VW> &a, co
 // there and is still faster) with a half batch, and so does bfloat16 in
 // 4-column lane chunks (8-byte row pieces, so a quarter batch holds as many
 // rows); bfloat16 in 8-column chunks runs 3 (133-168 VGPRs) with a half
-// batch; the one-lane residual form is left unconstrained.
+// batch, except the fused residual form, which runs 4 with a quarter batch
+// (it holds no repeated row; a few registers spill); the one-lane residual
+// form is left unconstrained.
 template <typename FT, int VW, int LPN, int NP, bool RESID, bool KRON>
 struct TileShape {
     static constexpr bool F32PLAIN = sizeof(FT) == 4 && NP >= 1 && (!RESID || LPN > 1);
@@ -311,10 +313,11 @@ struct TileShape {
     static constexpr bool F32MULTI = F32PLAIN && !RESID && !KRON && NP >= 2;
     static constexpr bool B16HALF = sizeof(FT) == 2 && VW == 4 && NP >= 1 && !RESID && !KRON;
     static constexpr bool B16ONE = sizeof(FT) == 2 && NP == 1 && !RESID && !KRON;
-    static constexpr int waves = F32MULTI ? 3 : (F32PLAIN || B16HALF) ? 4 : B16ONE ? 3
+    static constexpr bool B16RES = sizeof(FT) == 2 && RESID && NP >= 2;
+    static constexpr int waves = F32MULTI ? 3 : (F32PLAIN || B16HALF || B16RES) ? 4 : B16ONE ? 3
                                : (((LPN > 1 || !RESID) && !(sizeof(FT) == 2 && NP == 1)) ? 3 : 1);
     // registers of raw rows per lane for one gather batch
-    static constexpr int batch_regs = F32MULTI ? 64 : B16HALF ? 16
+    static constexpr int batch_regs = F32MULTI ? 64 : (B16HALF || B16RES) ? 16
                                     : (F32PLAIN || B16ONE || (sizeof(FT) == 2 && NP >= 2)) ? 32 : 64;
 };
 
