@@ -11,17 +11,19 @@ TOL_F32 = 1e-5
 TOL_BF16 = 2e-2
 
 
-_PROGRESS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
-                         "gpu_test_progress.log")
+# progress file for the tags (FCOO_TEST_PROGRESS; unset: none)
+_PROGRESS = os.environ.get("FCOO_TEST_PROGRESS", "")
 
 
 def tag(*parts):
     """Print what names the GPU step about to run (test case, shape, seed);
-    the line also goes to a progress file, since pytest holds captured
-    output back until a test ends."""
+    the line also goes to the progress file if one is set, since pytest
+    holds captured output back until a test ends."""
     line = " ".join(str(p) for p in ("[gpu]",) + parts)
     print(line, flush=True)
     sys.stdout.flush()
+    if not _PROGRESS:
+        return
     try:
         os.makedirs(os.path.dirname(_PROGRESS), exist_ok=True)
         with open(_PROGRESS, "a") as f:
