@@ -143,17 +143,27 @@ __global__ __launch_bounds__(256) void radix_scatter_kernel(const uint64_t *__re
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     const int tn = (int)(n - base < kSortTile ? n - base : kSortTile);
 
+    // the tile's pairs, all in flight at once (pair r * 256 + tid of the tile)
+    uint64_t kr[kSortItems];
+    uint32_t vr[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const int i = r * 256 + tid;
+        kr[r] = i < tn ? kin[base + i] : 0ull;
+        vr[r] = i < tn ? vin[base + i] : 0u;
+    }
     const int64_t hi = (int64_t)tid * ntiles + blockIdx.x;
     int total;
     s_toff[tid] = block_exclusive(hist[hi], s_w, total);
     s_glob[tid] = offs[hi];
     s_run[tid] = 0;
     const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const int i = r * 256 + tid;
         const bool valid = i < tn;
-        const uint64_t k = valid ? kin[base + i] : 0ull;
-        const uint32_t v = valid ? vin[base + i] : 0u;
+        const uint64_t k = kr[r];
+        const uint32_t v = vr[r];
         const int d = (int)((k >> shift) & 255u);
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_wcnt[q][tid] = 0;
